@@ -1,0 +1,248 @@
+"""FP64 CPU oracle for the ghost-cell pressure-Poisson solve.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the CPU-baseline leg of the benchmark; never by the product library.  It
+shares no code with the HIP path (its arithmetic lives in ``ibm_oracle.c``
+and in the plain numpy below).
+
+Pins (tests/test_oracle_*.py) tie it to the paper and to mathematics:
+closed-form eigenvector solutions, direct sparse solves of an independently
+assembled matrix, exact rational ray parity, trilinear reproduction and
+flat-wall equivalence.  The degenerate-stencil fallback and the membrane
+ghost rows away from a flat sheet are "parity unpinned" (only their counts
+and structural properties are checked).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ibm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+F_SOLID, F_GHOST, F_MGHOST, F_PIN = 1, 2, 4, 8
+F_CUTX, F_CUTY, F_CUTZ = 16, 32, 64
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _grid_args(xf, yf, zf):
+    return [ctypes.c_int(len(xf) - 1), ctypes.c_int(len(yf) - 1), ctypes.c_int(len(zf) - 1), _p(xf), _p(yf), _p(zf)]
+
+
+def _bodies_args(bodies):
+    kind = np.array([b.kind for b in bodies], dtype=np.int32)
+    nv = np.array([len(b.verts) for b in bodies], dtype=np.int32)
+    nt = np.array([len(b.tris) for b in bodies], dtype=np.int32)
+    V = np.ascontiguousarray(np.concatenate([b.verts.ravel() for b in bodies]) if bodies else np.zeros(3))
+    T = np.ascontiguousarray(np.concatenate([b.tris.ravel() for b in bodies]).astype(np.int32) if bodies
+                             else np.zeros(3, np.int32))
+    keep = (kind, nv, nt, V, T)
+    return keep, [ctypes.c_int(len(bodies)), _p(kind), _p(nv), _p(nt), _p(V), _p(T)]
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+def classify(xf, yf, zf, bodies) -> np.ndarray:
+    """uint8 flags[N] (x fastest): bit0 solid, bit1 closed ghost, bit2
+    membrane ghost, bit3 pin, bits 4-6 cut +x/+y/+z links."""
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    N = (len(xf) - 1) * (len(yf) - 1) * (len(zf) - 1)
+    flags = np.zeros(N, dtype=np.uint8)
+    keep, bargs = _bodies_args(bodies)
+    rc = lib().orc_classify(*_grid_args(xf, yf, zf), *bargs, _p(flags))
+    if rc != 0:
+        raise ValueError("orc_classify failed: %d" % rc)
+    return flags
+
+
+@dataclass
+class Stencils:
+    gcell: np.ndarray     # closed ghost cells, idx order
+    mcell: np.ndarray     # membrane ghost cells, idx order
+    mg_of: np.ndarray     # int32[N], membrane ghost index or -1
+    col: np.ndarray       # int32[(ng+nm), 8]
+    w: np.ndarray         # float64[(ng+nm), 8]
+    sG: np.ndarray
+    dlb: np.ndarray       # dl - beta_BI
+    rfl: np.ndarray       # bit0 fallback, bit1 derivative row, bit2 degenerate distance
+    geo: np.ndarray       # [(ng+nm), 12]: BI, IP, n, dl, beta_BI, dist
+    box: np.ndarray       # [(ng+nm), 3]
+
+    @property
+    def ng(self):
+        return len(self.gcell)
+
+    @property
+    def nm(self):
+        return len(self.mcell)
+
+    @property
+    def row_cell(self):
+        return np.ascontiguousarray(np.concatenate([self.gcell, self.mcell]).astype(np.int32))
+
+
+def ghost_lists(flags: np.ndarray):
+    gcell = np.nonzero(flags & F_GHOST)[0].astype(np.int32)
+    mcell = np.nonzero(flags & F_MGHOST)[0].astype(np.int32)
+    mg_of = np.full(len(flags), -1, dtype=np.int32)
+    mg_of[mcell] = np.arange(len(mcell), dtype=np.int32)
+    return gcell, mcell, mg_of
+
+
+def stencils(xf, yf, zf, bodies, flags) -> Stencils:
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    gcell, mcell, mg_of = ghost_lists(flags)
+    rows = np.ascontiguousarray(np.concatenate([gcell, mcell]).astype(np.int32))
+    mem = np.ascontiguousarray(np.concatenate([np.zeros(len(gcell), np.int32), np.ones(len(mcell), np.int32)]))
+    nr = len(rows)
+    col = np.full((max(nr, 1), 8), -1, dtype=np.int32)
+    w = np.zeros((max(nr, 1), 8))
+    sG = np.zeros(max(nr, 1))
+    dlb = np.zeros(max(nr, 1))
+    rfl = np.zeros(max(nr, 1), dtype=np.uint8)
+    geo = np.zeros((max(nr, 1), 12))
+    box = np.zeros((max(nr, 1), 3), dtype=np.int32)
+    keep, bargs = _bodies_args(bodies)
+    rc = lib().orc_ghost_stencils(*_grid_args(xf, yf, zf), *bargs, _p(flags), _p(mg_of), ctypes.c_int32(nr),
+                                  _p(rows), _p(mem), _p(col), _p(w), _p(sG), _p(dlb), _p(rfl), _p(geo), _p(box))
+    if rc != 0:
+        raise ValueError("orc_ghost_stencils failed: %d" % rc)
+    return Stencils(gcell, mcell, mg_of, col[:nr], w[:nr], sG[:nr], dlb[:nr], rfl[:nr], geo[:nr], box[:nr])
+
+
+def _sys_args(xf, yf, zf, flags, st: Stencils):
+    rows = st.row_cell
+    col = np.ascontiguousarray(st.col, dtype=np.int32)
+    w = np.ascontiguousarray(st.w)
+    sG = np.ascontiguousarray(st.sG)
+    keep = (rows, col, w, sG)
+    return keep, [*_grid_args(xf, yf, zf), _p(flags), _p(st.mg_of), ctypes.c_int32(st.ng), ctypes.c_int32(st.nm),
+                  _p(rows), _p(col), _p(w), _p(sG)]
+
+
+def apply(xf, yf, zf, flags, st: Stencils, x) -> np.ndarray:
+    """y = A x for the pinned operator (length N + nm)."""
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    x = _f64(x)
+    y = np.zeros_like(x)
+    keep, a = _sys_args(xf, yf, zf, flags, st)
+    lib().orc_apply(*a, _p(x), _p(y))
+    return y
+
+
+def assemble_rhs(xf, yf, zf, flags, st: Stencils, f, g=None) -> np.ndarray:
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    N = len(flags)
+    b = np.zeros(N + st.nm)
+    f = _f64(f)
+    gg = _f64(g) if g is not None else None
+    rows = st.row_cell
+    lib().orc_assemble_rhs(*_grid_args(xf, yf, zf), _p(flags), ctypes.c_int32(st.ng), ctypes.c_int32(st.nm),
+                           _p(rows), _p(_f64(st.sG)), _p(_f64(st.dlb)), _p(f), _p(gg), _p(b))
+    return b
+
+
+def gauge(xf, yf, zf, flags, nm, x) -> np.ndarray:
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    x = _f64(x).copy()
+    lib().orc_gauge(*_grid_args(xf, yf, zf), _p(flags), ctypes.c_int32(nm), _p(x))
+    return x
+
+
+def vcycle(xf, yf, zf, flags, st: Stencils, b, nu1=2, nu2=2, ncs=32) -> np.ndarray:
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    b = _f64(b)
+    x = np.zeros_like(b)
+    keep, a = _sys_args(xf, yf, zf, flags, st)
+    lib().orc_vcycle(*a, ctypes.c_int(nu1), ctypes.c_int(nu2), ctypes.c_int(ncs), _p(b), _p(x))
+    return x
+
+
+def num_levels(nx, ny, nz) -> int:
+    return lib().orc_num_levels(nx, ny, nz)
+
+
+@dataclass
+class SolveInfo:
+    rc: int
+    iters: int
+    relres: float
+    restarts: int
+    hist: np.ndarray
+
+
+def solve(xf, yf, zf, flags, st: Stencils, b, tol=1e-10, maxit=200, x0=None, nu1=2, nu2=2, ncs=32,
+          precond=True):
+    """MG-preconditioned BiCGSTAB on the pinned system; returns (x, info)."""
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    b = _f64(b)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    info = np.zeros(3)
+    hist = np.zeros(maxit + 1)
+    keep, a = _sys_args(xf, yf, zf, flags, st)
+    rc = lib().orc_solve(*a, _p(b), _p(x), ctypes.c_double(tol), ctypes.c_int(maxit), ctypes.c_int(nu1),
+                         ctypes.c_int(nu2), ctypes.c_int(ncs), ctypes.c_int(1 if precond else 0), _p(info), _p(hist))
+    it = int(info[0])
+    return x, SolveInfo(rc, it, float(info[1]), int(info[2]), hist[:it].copy())
+
+
+# --------------------------------------------------------------------------
+@dataclass
+class Setup:
+    xf: np.ndarray
+    yf: np.ndarray
+    zf: np.ndarray
+    flags: np.ndarray
+    st: Stencils
+
+    @property
+    def N(self):
+        return len(self.flags)
+
+
+def setup(xf, yf, zf, bodies) -> Setup:
+    flags = classify(xf, yf, zf, bodies)
+    st = stencils(xf, yf, zf, bodies, flags)
+    return Setup(_f64(xf), _f64(yf), _f64(zf), flags, st)
+
+
+def solve_problem(S: Setup, f, tol=1e-13, maxit=300, g=None):
+    """Full PPE pipeline: RHS assembly, pinned MG-BiCGSTAB, gauge."""
+    b = assemble_rhs(S.xf, S.yf, S.zf, S.flags, S.st, f, g)
+    x, info = solve(S.xf, S.yf, S.zf, S.flags, S.st, b, tol=tol, maxit=maxit)
+    xg = gauge(S.xf, S.yf, S.zf, S.flags, S.st.nm, x)
+    return xg, b, x, info

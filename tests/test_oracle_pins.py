@@ -1,0 +1,386 @@
+"""Pins of the FP64 oracle against mathematics (no GPU).
+
+P1 closed-form discrete eigenvector, P2 second-order convergence, P3 direct
+solve of an independently assembled matrix, P4 invariants, P5 flat-wall
+equivalence, P6 exact classification, P7 ghost geometry, P10 manufactured
+discrete solution.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_04335_amd import workloads as W
+from tests import refpy
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def setup_problem(xf, yf, zf, bodies):
+    return oracle.setup(xf, yf, zf, bodies)
+
+
+# ---------------------------------------------------------------- P1
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_p1_box_eigenvector_closed_form(n):
+    """On a uniform Neumann box, cos(pi x)cos(pi y)cos(pi z) at the centres is
+    an eigenvector with eigenvalue -(12/h^2) sin^2(pi h/2), so the discrete
+    solution is [(pi h/2)/sin(pi h/2)]^2 p_exact."""
+    f = W.uniform_faces(n)
+    S = setup_problem(f, f, f, [])
+    rhs = W.manufactured_rhs(f, f, f)
+    x, b, _, info = oracle.solve_problem(S, rhs, tol=1e-13)
+    assert info.rc == 0
+    h = 1.0 / n
+    ph = ((math.pi * h / 2) / math.sin(math.pi * h / 2)) ** 2 * W.manufactured_p(f, f, f)
+    assert rel(x[:S.N], ph) < 1e-11
+
+
+def test_p1_anisotropic_box():
+    """Same eigenvector on a 16 x 8 x 12 box with unequal spacings per axis."""
+    xf, yf, zf = W.uniform_faces(16), W.uniform_faces(8), W.uniform_faces(12)
+    S = setup_problem(xf, yf, zf, [])
+    rhs = W.manufactured_rhs(xf, yf, zf)
+    x, b, _, info = oracle.solve_problem(S, rhs, tol=1e-13)
+    lam = 0.0
+    for n in (16, 8, 12):
+        h = 1.0 / n
+        lam += -(4 / h ** 2) * math.sin(math.pi * h / 2) ** 2
+    ph = rhs / lam
+    assert rel(x[:S.N], ph) < 1e-11
+
+
+# ---------------------------------------------------------------- P2
+def _vw_err(x, p, vol, mask):
+    xm = x - np.sum(vol[mask] * x[mask]) / np.sum(vol[mask])
+    pm = p - np.sum(vol[mask] * p[mask]) / np.sum(vol[mask])
+    e = (xm - pm)[mask]
+    return math.sqrt(np.sum(vol[mask] * e ** 2) / np.sum(vol[mask])), float(np.abs(e).max())
+
+
+def test_p2_second_order_stretched_box():
+    errs = []
+    for n in (16, 32, 64):
+        # one fixed smooth map refined (beta of the 256^3 configuration)
+        f = W._tanh_faces(n, 1.35936)
+        S = setup_problem(f, f, f, [])
+        x, b, _, info = oracle.solve_problem(S, W.manufactured_rhs(f, f, f), tol=1e-11)
+        assert info.rc == 0
+        vol = refpy.vol(f, f, f)
+        errs.append(_vw_err(x[:S.N], W.manufactured_p(f, f, f), vol, np.ones(S.N, bool)))
+    o2 = [math.log2(a[0] / b[0]) for a, b in zip(errs[:-1], errs[1:])]
+    oi = [math.log2(a[1] / b[1]) for a, b in zip(errs[:-1], errs[1:])]
+    # L2 order tends to 2 (1.83, 1.94 measured); max-norm order is pre-asymptotic but rising
+    assert o2[0] > 1.75 and o2[1] > 1.9
+    assert oi[0] > 1.2 and oi[1] > 1.5 and oi[1] > oi[0]
+
+
+def test_p2_sphere_inhomogeneous_neumann():
+    """Sphere r=0.25 with g = grad(p_exact).n at the body intercept: the L2
+    error must fall at second order (>= 1.7) from 32^3 to 64^3."""
+    errs = []
+    for n in (32, 64):
+        f = W.uniform_faces(n)
+        bodies = [W.sphere((0.5, 0.5, 0.5), 0.25)]
+        S = setup_problem(f, f, f, bodies)
+        st = S.st
+        BI = st.geo[:, 0:3]
+        nrm = st.geo[:, 6:9]
+        gp = np.stack([-math.pi * np.sin(math.pi * BI[:, 0]) * np.cos(math.pi * BI[:, 1]) * np.cos(math.pi * BI[:, 2]),
+                       -math.pi * np.cos(math.pi * BI[:, 0]) * np.sin(math.pi * BI[:, 1]) * np.cos(math.pi * BI[:, 2]),
+                       -math.pi * np.cos(math.pi * BI[:, 0]) * np.cos(math.pi * BI[:, 1]) * np.sin(math.pi * BI[:, 2])], 1)
+        g = np.sum(gp * nrm, 1)
+        x, b, _, info = oracle.solve_problem(S, W.manufactured_rhs(f, f, f), tol=1e-12, g=g)
+        assert info.rc == 0
+        mask = (S.flags & 1) == 0
+        errs.append(_vw_err(x[:S.N], W.manufactured_p(f, f, f), refpy.vol(f, f, f), mask))
+    assert math.log2(errs[0][0] / errs[1][0]) >= 1.7
+
+
+# ---------------------------------------------------------------- P3
+@pytest.mark.parametrize("case", ["sphere12", "ellipsoid14", "c1"])
+def test_p3_direct_solve_matches(case):
+    if case == "sphere12":
+        f = W.uniform_faces(12)
+        xf = yf = zf = f
+        bodies = [W.sphere((0.5, 0.5, 0.5), 0.3, freq=4)]
+        rhs = W.noise_rhs(12 ** 3, 7)
+    elif case == "ellipsoid14":
+        xf, _ = W.stretched_faces(14)
+        yf, zf = W.uniform_faces(12), W.uniform_faces(10)
+        bodies = [W.ellipsoid((0.5, 0.5, 0.5), (0.3, 0.2, 0.15), W.rotation_zyx(0.3, 1.1, 2.0), freq=5)]
+        rhs = W.noise_rhs(14 * 12 * 10, 8)
+    else:
+        p = W.sphere_case(32)
+        xf, yf, zf, bodies, rhs = p.xf, p.yf, p.zf, p.bodies, p.f
+    S = setup_problem(xf, yf, zf, bodies)
+    A = refpy.assemble(xf, yf, zf, S.flags, S.st)
+    # operator parity on random input
+    rng = np.random.default_rng(1)
+    xr = rng.uniform(-1, 1, S.N + S.st.nm)
+    xr[~refpy.active_mask(S.flags, S.st.nm)] = 0.0
+    y_or = oracle.apply(xf, yf, zf, S.flags, S.st, xr)
+    assert rel(y_or, A @ xr) < 1e-14
+    x, b, xraw, info = oracle.solve_problem(S, rhs, tol=1e-13)
+    xd = refpy.solve_direct(A, b, S.flags, S.st.nm)
+    assert rel(xraw, xd) < 1e-10
+    assert np.linalg.norm(A @ xraw - b) / np.linalg.norm(b) < 1e-12
+
+
+# ---------------------------------------------------------------- P4
+def test_p4_invariants_c1():
+    p = W.sphere_case(32)
+    S = setup_problem(p.xf, p.yf, p.zf, p.bodies)
+    st = S.st
+    act = refpy.active_mask(S.flags, st.nm)
+    one = act.astype(float)
+    y = oracle.apply(p.xf, p.yf, p.zf, S.flags, st, one)
+    pin = int(np.nonzero(S.flags & 8)[0][0])
+    y_nopin = y.copy()
+    y_nopin[pin] = 0.0
+    assert np.abs(y_nopin).max() < 1e-13 * st.sG.max()
+    assert y[pin] < 0
+    ok = (st.rfl & 1) == 0
+    assert np.abs(st.w[ok].sum(1) - 1.0).max() < 1e-13
+    # solution mean zero after the gauge
+    x, b, _, info = oracle.solve_problem(S, p.f, tol=1e-12)
+    vol = refpy.vol(p.xf, p.yf, p.zf)
+    fl = (S.flags & 1) == 0
+    assert abs(np.sum(vol[fl] * x[:S.N][fl])) < 1e-12 * np.sum(vol[fl] * np.abs(x[:S.N][fl]))
+    # RHS: fluid part has zero volume-weighted mean once the pin entry is restored
+    fm = p.f[fl] - np.sum(vol[fl] * p.f[fl]) / np.sum(vol[fl])
+    assert np.allclose(b[:S.N][fl & ((S.flags & 8) == 0)], fm[((S.flags & 8) == 0)[fl]], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", ["c1", "c2_64"])
+def test_p4_trilinear_reproduction(case):
+    """For any trilinear phi: sum_value w_k phi(x_k) + beta_BI dphi/dn(BI) = phi(IP)."""
+    if case == "c1":
+        p = W.sphere_case(32)
+    else:
+        p = W.sphere_ellipsoid_case(64)
+    S = setup_problem(p.xf, p.yf, p.zf, p.bodies)
+    st = S.st
+    cs = [refpy.centres(p.xf), refpy.centres(p.yf), refpy.centres(p.zf)]
+    nx, ny = len(cs[0]), len(cs[1])
+    rng = np.random.default_rng(3)
+    ok = np.nonzero((st.rfl & 1) == 0)[0]
+    assert len(ok) > 0.95 * len(st.rfl)
+    for trial in range(3):
+        c = rng.uniform(-1, 1, 8)
+
+        def phi(x, y, z):
+            return c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * y + c[5] * y * z + c[6] * x * z + c[7] * x * y * z
+
+        def grad(x, y, z):
+            return np.stack([c[1] + c[4] * y + c[6] * z + c[7] * y * z,
+                             c[2] + c[4] * x + c[5] * z + c[7] * x * z,
+                             c[3] + c[5] * y + c[6] * x + c[7] * x * y], -1)
+        col = st.col[ok]
+        w = st.w[ok]
+        cell = np.where(col >= 0, col, 0)
+        xi, yi, zi = cell % nx, (cell // nx) % ny, cell // (nx * ny)
+        vals = phi(cs[0][xi], cs[1][yi], cs[2][zi])
+        lhs = np.sum(np.where(col >= 0, w * vals, 0.0), 1)
+        BI = st.geo[ok, 0:3]
+        IP = st.geo[ok, 3:6].copy()
+        for d in range(3):
+            IP[:, d] = np.clip(IP[:, d], cs[d][0], cs[d][-1])
+        nrm = st.geo[ok, 6:9]
+        lhs += st.geo[ok, 10] * np.sum(grad(BI[:, 0], BI[:, 1], BI[:, 2]) * nrm, 1)
+        rhs = phi(IP[:, 0], IP[:, 1], IP[:, 2])
+        assert np.abs(lhs - rhs).max() < 1e-11
+
+
+# ---------------------------------------------------------------- P5
+def test_p5_flat_wall_equals_truncated_box():
+    """A slab whose surface lies on the face plane z = 24/32 reproduces the
+    plain Neumann solution of the truncated 32 x 32 x 24 box."""
+    n = 32
+    f = W.uniform_faces(n)
+    slab = W.box((-0.5, -0.5, 0.75), (1.5, 1.5, 1.5))
+    S = setup_problem(f, f, f, [slab])
+    st = S.st
+    assert st.ng == n * n
+    # every image point is the mirrored fluid centre, weight 1 on it
+    assert np.all((st.rfl & 1) == 0)
+    wmax = st.w.max(1)
+    assert np.allclose(wmax, 1.0, atol=1e-14)
+    rng = np.random.default_rng(5)
+    rhs = rng.uniform(-1, 1, n ** 3)
+    x, b, _, info = oracle.solve_problem(S, rhs, tol=1e-13)
+    zt = W.uniform_faces(24, 0.75)
+    T = setup_problem(f, f, zt, [])
+    xt, bt, _, infot = oracle.solve_problem(T, rhs[: n * n * 24], tol=1e-13)
+    assert rel(x[: n * n * 24], xt) < 1e-10
+
+
+# ---------------------------------------------------------------- P6
+def _brute_case(name):
+    if name == "sphere_freq2":
+        f = W.uniform_faces(12)
+        return f, f, f, [W.sphere((0.5, 0.5, 0.5), 0.34, freq=2)]
+    if name == "ellipsoid_stretched":
+        xf, _ = W.stretched_faces(10)
+        return xf, W.uniform_faces(12), W.uniform_faces(14), [
+            W.ellipsoid((0.45, 0.5, 0.55), (0.35, 0.2, 0.25), W.rotation_zyx(0.4, 0.9, 2.2), freq=3)]
+    if name == "two_bodies_on_lattice":
+        # vertices exactly on cell-centre lattice lines: exercises the tie rule
+        f = W.uniform_faces(8)
+        return f, f, f, [W.box((0.1875, 0.1875, 0.1875), (0.5625, 0.6875, 0.4375)),
+                         W.sphere((0.6875, 0.6875, 0.6875), 0.2, freq=2)]
+    if name == "plate":
+        f = W.uniform_faces(12)
+        return f, f, f, [W.plate((0.5, 0.5, 0.5), 0.5, 0.6, 5, 6, 0.08, 0.7)]
+    if name == "plate_on_lattice":
+        f = W.uniform_faces(8)
+        return f, f, f, [W.plate((0.5, 0.5, 0.5625), 0.5, 0.5, 4, 4, 0.0, 0.0)]
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["sphere_freq2", "ellipsoid_stretched", "two_bodies_on_lattice", "plate",
+                                  "plate_on_lattice"])
+def test_p6_classification_matches_exact_rational_parity(name):
+    xf, yf, zf, bodies = _brute_case(name)
+    flags = oracle.classify(xf, yf, zf, bodies)
+    solid, cut = refpy.brute_flags(xf, yf, zf, bodies)
+    exp = refpy.expected_flags(xf, yf, zf, solid, cut)
+    assert np.array_equal(flags, exp)
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_p6_sphere_analytic_containment(n):
+    f = W.uniform_faces(n)
+    r = 0.25
+    flags = oracle.classify(f, f, f, [W.sphere((0.5, 0.5, 0.5), r)])
+    c = refpy.centres(f)
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    dist = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2).transpose(2, 1, 0).ravel()
+    # sagitta of the frequency-10 geodesic sphere, plus one lattice unit
+    v, t = W.geodesic_sphere(10)
+    edge = np.max(np.linalg.norm(v[t[:, 0]] - v[t[:, 1]], axis=1))
+    sag = r * (1 - math.cos(edge)) + 2.0 / 65536
+    solid = (flags & 1) != 0
+    assert np.all(solid[dist < r - sag])
+    assert not np.any(solid[dist > r + 2.0 / 65536])
+    h = 1.0 / n
+    shell = np.sum(np.abs(dist - r) < 1.8 * h)
+    assert abs(solid.sum() - 4 / 3 * math.pi * r ** 3 / h ** 3) < shell
+
+
+def test_p6_mirror_symmetry():
+    """The geodesic sphere keeps the coordinate mirror symmetries; on a
+    symmetric grid the classification must too (no lattice ties here)."""
+    f = W.uniform_faces(24)
+    flags = oracle.classify(f, f, f, [W.sphere((0.5, 0.5, 0.5), 0.3)])
+    s = ((flags & 3) != 0).reshape(24, 24, 24)
+    assert np.array_equal(s, s[::-1, :, :])
+    assert np.array_equal(s, s[:, ::-1, :])
+    assert np.array_equal(s, s[:, :, ::-1])
+
+
+# ---------------------------------------------------------------- P7
+def test_p7_ghost_geometry_sphere():
+    p = W.sphere_case(32)
+    S = setup_problem(p.xf, p.yf, p.zf, p.bodies)
+    st = S.st
+    cs = [refpy.centres(p.xf)] * 3
+    n = 32
+    G = np.stack([cs[0][st.gcell % n], cs[1][(st.gcell // n) % n], cs[2][st.gcell // (n * n)]], 1)
+    BI, IP, nrm = st.geo[:, 0:3], st.geo[:, 3:6], st.geo[:, 6:9]
+    r = np.linalg.norm(BI - 0.5, axis=1)
+    # every point of a facet is at least the facet-plane distance from the centre
+    v, t = W.geodesic_sphere(10)
+    nf = np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]])
+    rmin = 0.25 * np.min(np.abs(np.sum(nf * v[t[:, 0]], 1)) / np.linalg.norm(nf, axis=1))
+    assert np.all(r <= 0.25 + 1e-12) and np.all(r >= rmin - 1e-12)
+    assert np.allclose(np.linalg.norm(IP - G, axis=1), 2 * st.geo[:, 11], rtol=1e-12)
+    assert np.allclose(0.5 * (IP + G), BI, atol=1e-14)
+    # normals point out of the body
+    assert np.all(np.sum(nrm * (BI - 0.5), 1) > 0)
+    # ghost cells are inside the sphere, within one cell diagonal of the surface
+    rg = np.linalg.norm(G - 0.5, axis=1)
+    assert np.all(rg < 0.25 + 1e-9) and np.all(rg > 0.25 - math.sqrt(3) / n)
+
+
+# ---------------------------------------------------------------- P10
+def test_p10_manufactured_discrete_solution():
+    p = W.sphere_ellipsoid_case(48)
+    S = setup_problem(p.xf, p.yf, p.zf, p.bodies)
+    st = S.st
+    rng = np.random.default_rng(11)
+    xt = rng.uniform(-1, 1, S.N + st.nm)
+    xt[~refpy.active_mask(S.flags, st.nm)] = 0.0
+    xt[int(np.nonzero(S.flags & 8)[0][0])] = 0.0
+    b = oracle.apply(p.xf, p.yf, p.zf, S.flags, st, xt)
+    x, info = oracle.solve(p.xf, p.yf, p.zf, S.flags, st, b, tol=1e-13)
+    assert info.rc == 0
+    assert rel(x, xt) < 1e-9
+
+
+def test_unpreconditioned_and_preconditioned_agree():
+    p = W.sphere_case(16)
+    S = setup_problem(p.xf, p.yf, p.zf, p.bodies)
+    b = oracle.assemble_rhs(p.xf, p.yf, p.zf, S.flags, S.st, p.f)
+    x1, i1 = oracle.solve(p.xf, p.yf, p.zf, S.flags, S.st, b, tol=1e-13, maxit=2000, precond=False)
+    x2, i2 = oracle.solve(p.xf, p.yf, p.zf, S.flags, S.st, b, tol=1e-13)
+    assert i2.iters < i1.iters
+    assert rel(x1, x2) < 1e-10
+
+
+# ---------------------------------------------------------------- membranes
+def test_p3_membrane_direct_solve():
+    xf, _ = W.stretched_faces(14)
+    yf, zf = W.uniform_faces(12), W.uniform_faces(12)
+    bodies = [W.plate((0.5, 0.5, 0.5), 0.4, 0.6, 6, 9, 0.06, 0.9)]
+    S = setup_problem(xf, yf, zf, bodies)
+    assert S.st.nm > 0
+    A = refpy.assemble(xf, yf, zf, S.flags, S.st)
+    rng = np.random.default_rng(2)
+    xr = rng.uniform(-1, 1, S.N + S.st.nm)
+    assert rel(oracle.apply(xf, yf, zf, S.flags, S.st, xr), A @ xr) < 1e-14
+    rhs = W.noise_rhs(S.N, 9)
+    x, b, xraw, info = oracle.solve_problem(S, rhs, tol=1e-13)
+    assert info.rc == 0
+    xd = refpy.solve_direct(A, b, S.flags, S.st.nm)
+    assert rel(xraw, xd) < 1e-10
+
+
+def test_p5_flat_membrane_equals_masked_faces():
+    """A flat plate on the face plane z = 1/2 with its edges on face planes:
+    each membrane ghost takes the value of the cell across, so the fluid
+    solution equals the box with those z-faces closed."""
+    n = 12
+    f = W.uniform_faces(n)
+    # plate x in [3/12, 9/12], y in [2/12, 10/12], z = 6/12
+    pl = W.plate((0.5, 0.5, 0.5), 0.5, 8.0 / 12, 3, 4, 0.0, 0.0)
+    S = setup_problem(f, f, f, [pl])
+    st = S.st
+    assert st.nm == 2 * 6 * 8
+    # every ghost unknown takes the value of the cell across the sheet: one
+    # weight of 1 on the cell mirrored in z (the edge column, whose box holds a
+    # non-ghost node on the ghost's side, reaches it through the fallback)
+    across = np.where(st.mcell // (n * n) == 5, st.mcell + n * n, st.mcell - n * n)
+    k = np.argmax(np.abs(st.w), 1)
+    assert np.allclose(st.w[np.arange(st.nm), k], 1.0, atol=1e-14)
+    assert np.array_equal(st.col[np.arange(st.nm), k], across)
+    assert np.all(np.abs(st.w).sum(1) < 1 + 1e-13)
+    closed = set()
+    for j in range(2, 10):
+        for i in range(3, 9):
+            closed.add((2, i + n * (j + n * 5)))
+    rng = np.random.default_rng(4)
+    rhs = rng.uniform(-1, 1, n ** 3)
+    x, b, _, info = oracle.solve_problem(S, rhs, tol=1e-13)
+    assert info.rc == 0
+    A = refpy.assemble_masked_box(f, f, f, closed, pin=0)
+    vol = refpy.vol(f, f, f)
+    bb = rhs - np.sum(vol * rhs) / np.sum(vol)
+    bb[0] = 0.0
+    from scipy.sparse.linalg import spsolve
+    xm = spsolve(A.tocsc(), bb)
+    xm -= np.sum(vol * xm) / np.sum(vol)
+    assert rel(x[:S.N], xm) < 1e-10
