@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark: multigrid-preconditioned BiCGSTAB pressure solve on one MI355X.
+
+A step is one whole PPE solve (RHS assembly, pinned MG-BiCGSTAB to the
+tolerance, gauge) of the configured workload with its inputs resident in
+HBM.  Default workload: 512^3 tanh-stretched grid (ratio 1.05) around a
+cambered zero-thickness plate (40k triangles), uniform-noise RHS, mixed
+precision (FP32 V-cycle and inner BiCGSTAB with BF16 coarse right-hand
+sides inside FP64 iterative refinement) to 1e-8 relative residual; the plain
+FP64 solve of the same system is timed beside it.
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 is refused.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MG-BiCGSTAB pressure solve Mpts/s to 1e-8 resid, % HBM peak; serve p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_problem(cfg):
+    from paper_2605_04335_amd import workloads as W
+    if cfg == "c3":
+        p = W.membrane_case(512)
+        p.tol = 1e-8
+        return p, "membrane plate 512^3 tanh-stretched, 40k triangles, noise RHS, mixed MG-BiCGSTAB to 1e-8"
+    if cfg == "c2":
+        p = W.sphere_ellipsoid_case(256)
+        p.tol = 1e-8
+        p.mixed = True
+        return p, "sphere+ellipsoid 256^3 tanh-stretched, noise RHS, mixed MG-BiCGSTAB to 1e-8"
+    if cfg == "c4":
+        p = W.spheres_case(1024)
+        p.mixed = True
+        return p, "20 spheres 1024^3 uniform, Gaussian-bump RHS, mixed MG-BiCGSTAB to 1e-8"
+    if cfg == "c1":
+        p = W.sphere_case(32)
+        p.tol = 1e-8
+        p.mixed = True
+        return p, "sphere 32^3 uniform, manufactured RHS, mixed MG-BiCGSTAB to 1e-8"
+    raise SystemExit("unknown config " + cfg)
+
+
+def cpu_baseline(cfg, budget_s):
+    """The FP64 oracle on a bounded sample of the same workload recipe."""
+    import oracle
+    from paper_2605_04335_amd import workloads as W
+    n = {"c3": 256, "c2": 128, "c4": 256, "c1": 32}[cfg]
+    if cfg == "c3":
+        p = W.membrane_case(n)
+    elif cfg == "c2":
+        p = W.sphere_ellipsoid_case(n)
+    elif cfg == "c4":
+        p = W.spheres_case(n)
+    else:
+        p = W.sphere_case(n)
+    t0 = time.time()
+    S = oracle.setup(p.xf, p.yf, p.zf, p.bodies)
+    t_setup = time.time() - t0
+    b = oracle.assemble_rhs(S.xf, S.yf, S.zf, S.flags, S.st, p.f)
+    t0 = time.time()
+    x, info = oracle.solve(S.xf, S.yf, S.zf, S.flags, S.st, b, tol=1e-8, maxit=200)
+    t = time.time() - t0
+    N = p.npts
+    return {"value": N / t / 1e6, "unit": "Mpts/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "same recipe at %d^3 (%d points): FP64 oracle MG-BiCGSTAB to 1e-8, %d iterations, %.1f s solve"
+                      " (+%.1f s setup)" % (n, N, info.iters, t, t_setup)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the PPE solve on a single MI355X; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    import paper_2605_04335_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p, desc = make_problem(args.config)
+    nx, ny, nz = p.shape
+    N = p.npts
+    log("workload", desc)
+    t0 = time.time()
+    flags, cst = P.classify(p.xf, p.yf, p.zf, p.bodies)
+    st = P.build_ghost_stencils(p.xf, p.yf, p.zf, p.bodies, flags)
+    ng, nm, nfb = st.info()
+    solm = P.Solver(p.xf, p.yf, p.zf, flags, st, precision=P.PREC_MIXED, tol=p.tol, max_iter=60)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    log("setup %.2f s: ghosts %d, membrane ghosts %d, fallback %d" % (setup_s, ng, nm, nfb))
+    f = torch.from_numpy(p.f).to(dev)
+
+    for _ in range(args.warmup):
+        x, stm = solm.solve(f)
+        log("warmup mixed: its %d outer %d rel %.2e %.1f ms" % (stm.iterations, stm.outer_steps, stm.rel_residual,
+                                                                stm.solve_ms))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev_ms = []
+    for k in range(args.steps):
+        x, stm = solm.solve(f)
+        dev_ms.append(stm.solve_ms)
+        log("step %d: its %d outer %d rel %.2e %.1f ms" % (k, stm.iterations, stm.outer_steps, stm.rel_residual,
+                                                           stm.solve_ms))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = N / (ms_per_step / 1e3) / 1e6
+
+    # dominant kernel, timed per launch with HIP events on the library's stream
+    roof = None
+    kern_ms = {}
+    for kid, name in ((0, "k0_sweep"), (1, "k0_apply"), (2, "k_xr_update")):
+        P.lib().poisson_kernel_timing(solm.h, kid, 1, None, None)
+        solm.solve(f)
+        tot = P.ctypes.c_double()
+        cnt = P.ctypes.c_int64()
+        P.lib().poisson_kernel_timing(solm.h, -1, 1, P.ctypes.byref(tot), P.ctypes.byref(cnt))
+        kern_ms[name] = (tot.value, cnt.value)
+    tot, cnt = kern_ms["k0_sweep"]
+    if cnt:
+        avg_ms = tot / cnt
+        T = 4  # FP32 inner vectors
+        # red/black half-sweep: other-colour neighbours, this colour's RHS, write this colour (T each per
+        # half of the cells) and the flag byte of every cell
+        bytes_launch = (1.5 * T + 1.0) * N
+        ach = bytes_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k0_sweep<float>",
+                "avg_launch_ms": round(avg_ms, 4), "launches_per_solve": cnt,
+                "algorithmic_bytes_per_launch": int(bytes_launch)}
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32+bf16", "data": "synthetic",
+           "config": {"workload": desc, "grid": [nx, ny, nz], "points": N, "tol": p.tol,
+                      "precision": "mixed (FP32/BF16 V-cycle and inner BiCGSTAB, FP64 refinement)",
+                      "iterations": stm.iterations, "outer_steps": stm.outer_steps,
+                      "rel_residual": stm.rel_residual, "device_ms_per_solve": round(float(np.median(dev_ms)), 3),
+                      "setup_s": round(setup_s, 2), "ghosts": ng, "membrane_ghosts": nm, "fallback_rows": nfb},
+           "roofline": roof,
+           "kernel_ms": {k: {"total_ms": round(v[0], 3), "launches": v[1]} for k, v in kern_ms.items()}}
+
+    if not args.no_fp64:
+        del solm
+        torch.cuda.empty_cache()
+        sol64 = P.Solver(p.xf, p.yf, p.zf, flags, st, precision=P.PREC_FP64, tol=p.tol, max_iter=100)
+        x64, s64 = sol64.solve(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(1, min(3, args.steps))
+        for _ in range(reps):
+            x64, s64 = sol64.solve(f)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) / reps * 1e3
+        err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        out["config"]["fp64"] = {"ms_per_solve": round(ms64, 3), "Mpts_s": round(N / ms64 * 1e3 / 1e6, 2),
+                                 "iterations": s64.iterations, "rel_residual": s64.rel_residual}
+        out["config"]["mixed_speedup_vs_fp64"] = round(ms64 / ms_per_step, 3)
+        out["config"]["mixed_rel_error_vs_fp64"] = err
+        log("fp64: %.1f ms/solve, %d its; mixed speed-up %.2fx, rel error %.2e" % (ms64, s64.iterations,
+                                                                                   ms64 / ms_per_step, err))
+    if rank == 0 and not args.no_cpu:
+        try:
+            out["cpu_baseline"] = cpu_baseline(args.config, 30)
+        except Exception as e:  # reported, never fatal
+            out["cpu_baseline"] = {"value": None, "error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,260 @@
+/*
+ * ibm_poisson.h -- C ABI of the MI355X (gfx950) ghost-cell immersed-boundary
+ * pressure-Poisson library (libibmpoisson.so).
+ *
+ * The library implements the pressure Poisson equation (PPE) step of a
+ * fractional-step, sharp-interface immersed-boundary flow solver (Kumar,
+ * Seo, Mittal, Romero, Fatica, "GPU-Accelerated Simulations of Moving
+ * Boundary Problems and Fluid-Structure Interaction at Extreme Scales",
+ * arXiv 2605.04335; Sec. 2.1 fractional step and PPE by BiCGStab, Sec. 2.5
+ * the three GPU modules: iblanking, ghost-cell boundary conditions, sparse
+ * matrix-free + ELLPACK solvers).  Every step runs in HIP kernels on the
+ * device; this header has no HIP or framework types.
+ *
+ * Conventions
+ *   - Grid: nx*ny*nz cells, faces xf[0..nx] etc. strictly increasing, each
+ *     dimension >= 4.  Fields are x-fastest: idx = i + nx*(j + ny*k).
+ *   - Unknown vectors have length N + n_mghost: the N cell values followed
+ *     by one ghost unknown per membrane ghost cell (in cell-index order).
+ *   - "host" pointers are read during the call only (copied); "device"
+ *     pointers are caller-owned device memory that must outlive the work
+ *     enqueued on the given stream.  A stream argument is a hipStream_t
+ *     passed as void* (NULL = the null stream).
+ *   - Every function returns 0 on success or a negative IBM_E* code; the
+ *     message of the last failure on the calling thread is ibm_last_error().
+ */
+#ifndef IBM_POISSON_H
+#define IBM_POISSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IBM_OK 0
+#define IBM_EINVAL (-1)      /* null pointer, bad sizes, non-increasing faces, body too far out */
+#define IBM_EGEOM (-2)       /* bad mesh indices, degenerate triangle, no fluid cell */
+#define IBM_ENOMEM (-3)      /* device allocation failed, workspace too small, request cannot be admitted */
+#define IBM_EHIP (-4)        /* HIP runtime error (message carries the HIP error string) */
+#define IBM_ENOCONV (-5)     /* iteration limit reached; x holds the last iterate, stats are filled */
+#define IBM_EBREAKDOWN (-6)  /* BiCGSTAB breakdown or non-finite values */
+#define IBM_EAGAIN (-7)      /* poll: request not finished */
+#define IBM_ENOTFOUND (-8)   /* poll: unknown ticket */
+
+#define IBM_KIND_CLOSED 0    /* watertight, outward-oriented triangulated body */
+#define IBM_KIND_MEMBRANE 1  /* zero-thickness open sheet */
+
+/* flag bits of the classification (one byte per cell) */
+#define IBM_F_SOLID 0x01
+#define IBM_F_GHOST 0x02     /* solid cell with a fluid face neighbour */
+#define IBM_F_MGHOST 0x04    /* fluid cell with at least one membrane-cut link */
+#define IBM_F_PIN 0x08       /* the gauge cell: first fluid non-membrane-ghost cell */
+#define IBM_F_CUTX 0x10      /* link (i,j,k)-(i+1,j,k) crosses a membrane */
+#define IBM_F_CUTY 0x20
+#define IBM_F_CUTZ 0x40
+
+typedef struct ibm_grid {
+    int32_t nx, ny, nz;
+    const double *xf, *yf, *zf; /* host, lengths nx+1, ny+1, nz+1 */
+} ibm_grid;
+
+typedef struct ibm_body {
+    int32_t n_vert, n_tri, kind; /* kind: IBM_KIND_* */
+    const double *vert;          /* host, n_vert*3 coordinates */
+    const int32_t *tri;          /* host, n_tri*3 vertex indices */
+} ibm_body;
+
+typedef struct ibm_class_stats {
+    int64_t n_solid, n_ghost, n_mghost, n_cut_links, pin;
+} ibm_class_stats;
+
+typedef struct ibm_stencils ibm_stencils; /* opaque, library-owned, device-resident */
+typedef struct poisson_ctx poisson_ctx;   /* opaque, library-owned */
+
+#define IBM_PREC_FP64 0
+#define IBM_PREC_MIXED 1
+
+typedef struct poisson_opts {
+    int32_t precision;      /* IBM_PREC_FP64 or IBM_PREC_MIXED */
+    double tol;             /* relative true residual ||b - A x|| / ||b|| */
+    int32_t max_iter;       /* BiCGSTAB iterations (FP64) / inner iterations per outer step (mixed) */
+    int32_t nu1, nu2;       /* pre/post smoothing steps of the V-cycle */
+    int32_t coarse_sweeps;  /* red-black sweeps on the coarsest level */
+    double inner_tol;       /* mixed: relative tolerance of each inner solve */
+    int32_t max_outer;      /* mixed: outer refinement steps */
+    int32_t use_graph;      /* replay each iteration as a captured HIP graph */
+} poisson_opts;
+
+typedef struct poisson_stats {
+    int32_t iterations;      /* BiCGSTAB iterations (summed over outer steps when mixed) */
+    int32_t outer_steps;     /* mixed: refinement steps taken */
+    int32_t status;          /* same code as the return value */
+    int32_t levels;          /* multigrid levels */
+    double rel_residual;     /* final true relative residual, FP64 */
+    double pin_residual;     /* unpinned-operator residual at the pin (inconsistency of the RHS) */
+    double solve_ms;         /* device time of the whole solve (events on the stream) */
+    int64_t n_fallback;      /* ghost rows that took the first-order fallback */
+} poisson_stats;
+
+/* Defaults: FP64, tol 1e-10, 200 iterations, V(2,2), 32 coarse sweeps,
+ * inner_tol 1e-5, max_outer 10, graphs on. */
+void poisson_default_opts(poisson_opts *opts);
+
+/*
+ * ibm_classify -- "iblanking" (Sec. 2.5, module 1): voxel classification of
+ * the grid against triangulated bodies.  Closed bodies: a cell is solid iff
+ * the ray along +x through its centre crosses the body an odd number of
+ * times before the centre, counted with exact integer predicates on a
+ * 2^16-per-longest-edge lattice and a top-left tie rule.  Membranes: a link
+ * between face neighbours is cut iff an odd number of membrane triangles
+ * cross it.  Then ghost, membrane-ghost, cut and pin bits (see IBM_F_*).
+ *   grid, bodies (host, copied); flags_dev: device uint8[N], written;
+ *   st (host, may be NULL): counts.  Bodies must lie within one domain length
+ *   of the domain.  Stream-ordered; synchronises once to read the counts.
+ */
+int32_t ibm_classify(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body, uint8_t *flags_dev,
+                     ibm_class_stats *st, void *stream);
+
+/*
+ * ibm_build_ghost_stencils -- ghost-cell boundary rows (Sec. 2.5, module 2;
+ * GCM of Mittal et al. 2008): for each closed ghost cell and each membrane
+ * ghost unknown, the body intercept (closest point on the body surface of
+ * the same kind), the image point mirrored through it, and the trilinear
+ * image-point weights of a homogeneous-Neumann row, from an 8x8 FP64 LU
+ * solve with partial pivoting per ghost (the batched inversions of Sec. 2.5).
+ *   flags_dev: the output of ibm_classify; *out receives a library-owned
+ *   table (free with ibm_stencils_free).  Synchronises to size the table.
+ */
+int32_t ibm_build_ghost_stencils(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body,
+                                 const uint8_t *flags_dev, ibm_stencils **out, void *stream);
+
+/* Row counts of a stencil table (any pointer may be NULL). */
+int32_t ibm_stencils_info(const ibm_stencils *s, int64_t *n_ghost, int64_t *n_mghost, int64_t *n_fallback);
+
+/*
+ * Host copies of the table, rows = n_ghost closed ghosts then n_mghost
+ * membrane ghosts, both in cell order: cell[rows]; col[rows*8] value
+ * columns (cell index or N + membrane index, -1 unused or derivative node);
+ * w[rows*8]; sG[rows] row scale; dlb[rows] = dl - beta_BI (the row's RHS is
+ * sG*dlb*g); rflags[rows] bit0 fallback, bit1 derivative row, bit2
+ * degenerate distance; geo[rows*12] (may be NULL): BI, IP, n, dl, beta_BI,
+ * distance.  All arrays are caller-allocated host memory.
+ */
+int32_t ibm_stencils_export(const ibm_stencils *s, int32_t *cell, int32_t *col, double *w, double *sG, double *dlb,
+                            uint8_t *rflags, double *geo);
+
+void ibm_stencils_free(ibm_stencils *s);
+
+/*
+ * poisson_setup -- builds the solver for one classified grid: copies the
+ * flags and the ghost rows into a device-resident level-0 operator
+ * (matrix-free 7-point bulk + ELL irregular rows, Sec. 2.5 module 3), the
+ * multigrid hierarchy and the Krylov work vectors, all in library-owned
+ * device memory.  *workspace_bytes (may be NULL) receives that footprint.
+ * flags_dev and the stencil table are not referenced after the call.
+ */
+int32_t poisson_setup(const ibm_grid *grid, const uint8_t *flags_dev, const ibm_stencils *st,
+                      const poisson_opts *opts, size_t *workspace_bytes, poisson_ctx **out);
+
+/* Device bytes a poisson_setup of this grid would hold (for admission). */
+int32_t poisson_workspace_estimate(int32_t nx, int32_t ny, int32_t nz, int64_t n_rows, int32_t precision,
+                                   size_t *bytes);
+
+/*
+ * poisson_solve -- the PPE solve: RHS assembly (fluid f projected to zero
+ * volume-weighted mean, pin row 0, ghost rows sG*dlb*g), right-preconditioned
+ * BiCGSTAB (van der Vorst 1992) with a geometric-multigrid V-cycle on the
+ * pinned system, FP64 (or mixed: FP32/BF16 inner solves inside FP64
+ * iterative refinement), then the gauge (volume-weighted fluid mean removed).
+ *   f_dev: device double[N]; g_dev: device double[n_ghost+n_mghost] or NULL
+ *   (homogeneous Neumann); x_dev: device double[N+n_mghost], output.
+ * Blocks the calling thread until done.  Returns IBM_ENOCONV with the last
+ * iterate in x_dev when the iteration limit is hit.
+ */
+int32_t poisson_solve(poisson_ctx *ctx, const double *f_dev, const double *g_dev, double *x_dev,
+                      poisson_stats *stats, void *stream);
+
+/* y = A x with the pinned operator (device double[N+n_mghost] each). */
+int32_t poisson_apply(poisson_ctx *ctx, const double *x_dev, double *y_dev, void *stream);
+
+/* b = assembled right-hand side for raw input f (and g or NULL). */
+int32_t poisson_assemble_rhs(poisson_ctx *ctx, const double *f_dev, const double *g_dev, double *b_dev, void *stream);
+
+/* x = M^{-1} b: one FP64 V-cycle of the preconditioner, including the
+ * compensating sink at the pin and the shift to a zero pin value. */
+int32_t poisson_precond(poisson_ctx *ctx, const double *b_dev, double *x_dev, void *stream);
+
+/* Solve an already assembled pinned system A x = b (no projection, no
+ * gauge); x_dev is the output.  For parity tests with manufactured b. */
+int32_t poisson_solve_assembled(poisson_ctx *ctx, const double *b_dev, double *x_dev, poisson_stats *stats,
+                                void *stream);
+
+/* Per-launch device timing of one kernel of the solve, for roofline
+ * reports: kernel 0 = level-0 red/black Gauss-Seidel half-sweep, 1 = level-0
+ * operator apply inside BiCGSTAB, 2 = the fused x/r update; -1 = off.  While
+ * a kernel is selected, solves run without graph replay and bracket each of
+ * its launches with HIP events on the solve stream.  Returns (and with reset
+ * != 0 clears) the accumulated milliseconds and launch count, then selects
+ * `kernel` for the following solves. */
+int32_t poisson_kernel_timing(poisson_ctx *ctx, int32_t kernel, int32_t reset, double *total_ms, int64_t *launches);
+
+/* Multigrid level count and unknown counts of a context (any pointer may be NULL). */
+int32_t poisson_level_info(poisson_ctx *ctx, int32_t *levels, int64_t *n_unknowns, int64_t *n_ghost,
+                           int64_t *n_mghost);
+
+void poisson_destroy(poisson_ctx *ctx);
+
+/* ------------------------------------------------------------------ serving
+ * A persistent scheduler thread owns one device and runs many solves at
+ * once (continuous batching at BiCGSTAB-iteration granularity, one stream
+ * per active solve).  Requests are admitted while the number of active
+ * solves is below max_slots and the summed footprints fit hbm_budget;
+ * finished solves release their slot and memory at once.
+ */
+typedef struct poisson_server poisson_server;
+
+typedef struct poisson_server_opts {
+    size_t hbm_budget;   /* bytes of device memory the active solves may hold */
+    int32_t max_slots;   /* concurrently active solves */
+    int32_t device;      /* HIP device ordinal */
+} poisson_server_opts;
+
+typedef struct poisson_request {
+    ibm_grid grid;             /* host arrays, copied at submit */
+    const ibm_body *bodies;    /* host, copied at submit */
+    int32_t n_body;
+    const double *f;           /* host double[N], copied at submit */
+    poisson_opts opts;
+} poisson_request;
+
+#define IBM_REQ_QUEUED 0
+#define IBM_REQ_RUNNING 1
+#define IBM_REQ_DONE 2
+#define IBM_REQ_FAILED 3
+
+typedef struct poisson_req_times {
+    double submit_ms, admit_ms, done_ms; /* on the server's steady clock, from server start */
+} poisson_req_times;
+
+int32_t poisson_server_create(const poisson_server_opts *opts, poisson_server **out);
+/* Enqueue a request; never blocks on the GPU.  *ticket identifies it. */
+int32_t poisson_submit(poisson_server *srv, const poisson_request *req, uint64_t *ticket);
+/* Non-blocking: IBM_EAGAIN while queued or running; on completion copies the
+ * solution (host double[N + n_mghost], may be NULL) and stats, frees the
+ * request and returns its solve status.  *state (may be NULL) gets IBM_REQ_*.
+ * x_len is the capacity of x_out in doubles. */
+int32_t poisson_poll(poisson_server *srv, uint64_t ticket, double *x_out, int64_t x_len, poisson_stats *stats,
+                     poisson_req_times *times, int32_t *state);
+/* Block until every submitted request has finished. */
+int32_t poisson_server_drain(poisson_server *srv);
+void poisson_server_destroy(poisson_server *srv);
+
+const char *ibm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBM_POISSON_H */

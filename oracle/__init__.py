@@ -246,3 +246,8 @@ def solve_problem(S: Setup, f, tol=1e-13, maxit=300, g=None):
     x, info = solve(S.xf, S.yf, S.zf, S.flags, S.st, b, tol=tol, maxit=maxit)
     xg = gauge(S.xf, S.yf, S.zf, S.flags, S.st.nm, x)
     return xg, b, x, info
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(lib().orc_threads())

@@ -1216,3 +1216,10 @@ done:
     grid_free(&S.g);
     return rc;
 }
+
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

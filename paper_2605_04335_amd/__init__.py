@@ -1,0 +1,348 @@
+"""Python binding of libibmpoisson (MI355X / gfx950).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  PyTorch provides device memory (tensors) and streams.  The
+library must have been built (``python -m paper_2605_04335_amd.build`` or
+``__graft_entry__.build()``); importing this module fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibmpoisson.so")
+
+IBM_OK, IBM_EINVAL, IBM_EGEOM, IBM_ENOMEM, IBM_EHIP, IBM_ENOCONV, IBM_EBREAKDOWN, IBM_EAGAIN, IBM_ENOTFOUND = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+PREC_FP64, PREC_MIXED = 0, 1
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int32_p = ctypes.POINTER(ctypes.c_int32)
+
+
+class IbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("xf", _c_double_p), ("yf", _c_double_p), ("zf", _c_double_p)]
+
+
+class _Body(ctypes.Structure):
+    _fields_ = [("n_vert", ctypes.c_int32), ("n_tri", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("vert", _c_double_p), ("tri", _c_int32_p)]
+
+
+class _ClassStats(ctypes.Structure):
+    _fields_ = [("n_solid", ctypes.c_int64), ("n_ghost", ctypes.c_int64), ("n_mghost", ctypes.c_int64),
+                ("n_cut_links", ctypes.c_int64), ("pin", ctypes.c_int64)]
+
+
+class PoissonOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class PoissonStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("outer_steps", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("pin_residual", ctypes.c_double),
+                ("solve_ms", ctypes.c_double), ("n_fallback", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("grid", _Grid), ("bodies", ctypes.POINTER(_Body)), ("n_body", ctypes.c_int32),
+                ("f", _c_double_p), ("opts", PoissonOpts)]
+
+
+class ReqTimes(ctypes.Structure):
+    _fields_ = [("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
+
+
+EXPORTS = ["ibm_classify", "ibm_build_ghost_stencils", "ibm_stencils_info", "ibm_stencils_export",
+           "ibm_stencils_free", "poisson_default_opts", "poisson_setup", "poisson_workspace_estimate",
+           "poisson_solve", "poisson_apply", "poisson_assemble_rhs", "poisson_precond", "poisson_solve_assembled",
+           "poisson_destroy", "poisson_server_create", "poisson_submit", "poisson_poll", "poisson_server_drain",
+           "poisson_server_destroy", "ibm_last_error"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libibmpoisson.so is not built (%s); run paper_2605_04335_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.ibm_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "ibm_last_error" and hasattr(L, name):
+                getattr(L, name).restype = ctypes.c_int32
+        L.ibm_stencils_free.restype = None
+        L.poisson_destroy.restype = None
+        L.poisson_default_opts.restype = None
+        if hasattr(L, "poisson_server_destroy"):
+            L.poisson_server_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = lib().ibm_last_error().decode(errors="replace")
+        raise IbmError(rc, "%s: %s" % (what, msg))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_c_double_p)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _tptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class _GridArgs:
+    def __init__(self, xf, yf, zf):
+        self.arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (xf, yf, zf)]
+        self.g = _Grid(len(self.arrs[0]) - 1, len(self.arrs[1]) - 1, len(self.arrs[2]) - 1,
+                       _dptr(self.arrs[0]), _dptr(self.arrs[1]), _dptr(self.arrs[2]))
+
+    @property
+    def N(self):
+        return self.g.nx * self.g.ny * self.g.nz
+
+
+class _BodyArgs:
+    def __init__(self, bodies):
+        self.keep = []
+        n = len(bodies)
+        self.arr = (_Body * max(n, 1))()
+        for i, b in enumerate(bodies):
+            v = np.ascontiguousarray(b.verts, dtype=np.float64).ravel()
+            t = np.ascontiguousarray(b.tris, dtype=np.int32).ravel()
+            self.keep += [v, t]
+            self.arr[i] = _Body(len(v) // 3, len(t) // 3, int(b.kind), _dptr(v), t.ctypes.data_as(_c_int32_p))
+        self.n = n
+
+
+def default_opts(**kw) -> PoissonOpts:
+    o = PoissonOpts()
+    lib().poisson_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PREC_MIXED if v == "mixed" else PREC_FP64
+        setattr(o, k, v)
+    return o
+
+
+# ------------------------------------------------------------------ geometry
+def classify(xf, yf, zf, bodies, device="cuda"):
+    """Device uint8 flags (torch) and counts."""
+    import torch
+    G = _GridArgs(xf, yf, zf)
+    B = _BodyArgs(bodies)
+    flags = torch.empty(G.N, dtype=torch.uint8, device=device)
+    st = _ClassStats()
+    _check(lib().ibm_classify(ctypes.byref(G.g), B.arr, ctypes.c_int32(B.n), _tptr(flags), ctypes.byref(st),
+                              _stream()), "ibm_classify")
+    return flags, {k: getattr(st, k) for k, _ in st._fields_}
+
+
+class Stencils:
+    def __init__(self, handle, N):
+        self.h = handle
+        self.N = N
+
+    def info(self):
+        ng, nm, nf = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ibm_stencils_info(self.h, ctypes.byref(ng), ctypes.byref(nm), ctypes.byref(nf)), "info")
+        return ng.value, nm.value, nf.value
+
+    def export(self):
+        ng, nm, nf = self.info()
+        rows = ng + nm
+        out = dict(cell=np.zeros(rows, np.int32), col=np.zeros((rows, 8), np.int32), w=np.zeros((rows, 8)),
+                   sG=np.zeros(rows), dlb=np.zeros(rows), rfl=np.zeros(rows, np.uint8), geo=np.zeros((rows, 12)))
+        if rows:
+            _check(lib().ibm_stencils_export(self.h, out["cell"].ctypes.data_as(_c_int32_p),
+                                             out["col"].ctypes.data_as(_c_int32_p), _dptr(out["w"]),
+                                             _dptr(out["sG"]), _dptr(out["dlb"]),
+                                             out["rfl"].ctypes.data_as(ctypes.c_void_p), _dptr(out["geo"])),
+                   "export")
+        out["ng"], out["nm"], out["nfallback"] = ng, nm, nf
+        return out
+
+    def close(self):
+        if self.h:
+            lib().ibm_stencils_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_ghost_stencils(xf, yf, zf, bodies, flags) -> Stencils:
+    G = _GridArgs(xf, yf, zf)
+    B = _BodyArgs(bodies)
+    h = ctypes.c_void_p()
+    _check(lib().ibm_build_ghost_stencils(ctypes.byref(G.g), B.arr, ctypes.c_int32(B.n), _tptr(flags),
+                                          ctypes.byref(h), _stream()), "ibm_build_ghost_stencils")
+    return Stencils(h, G.N)
+
+
+# ------------------------------------------------------------------ solver
+class Solver:
+    """A poisson_ctx: level-0 operator, multigrid hierarchy and work vectors."""
+
+    def __init__(self, xf, yf, zf, flags, stencils: Stencils, opts: Optional[PoissonOpts] = None, **kw):
+        self.G = _GridArgs(xf, yf, zf)
+        self.opts = opts if opts is not None else default_opts(**kw)
+        ng, nm, nf = stencils.info()
+        self.N, self.nm, self.ng = self.G.N, nm, ng
+        self.h = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t()
+        _check(lib().poisson_setup(ctypes.byref(self.G.g), _tptr(flags), stencils.h, ctypes.byref(self.opts),
+                                   ctypes.byref(nbytes), ctypes.byref(self.h)), "poisson_setup")
+        self.workspace_bytes = nbytes.value
+
+    @property
+    def n_unknowns(self):
+        return self.N + self.nm
+
+    def _vec(self, device="cuda"):
+        import torch
+        return torch.zeros(self.n_unknowns, dtype=torch.float64, device=device)
+
+    def solve(self, f, g=None, x=None, check=True):
+        import torch
+        assert f.dtype == torch.float64 and f.is_cuda and f.is_contiguous() and f.numel() == self.N
+        if x is None:
+            x = self._vec(f.device)
+        st = PoissonStats()
+        rc = lib().poisson_solve(self.h, _tptr(f), _tptr(g) if g is not None else None, _tptr(x),
+                                 ctypes.byref(st), _stream())
+        if check:
+            _check(rc, "poisson_solve")
+        return x, st
+
+    def solve_assembled(self, b, x=None, check=True):
+        if x is None:
+            x = self._vec(b.device)
+        st = PoissonStats()
+        rc = lib().poisson_solve_assembled(self.h, _tptr(b), _tptr(x), ctypes.byref(st), _stream())
+        if check:
+            _check(rc, "poisson_solve_assembled")
+        return x, st
+
+    def apply(self, x, y=None):
+        if y is None:
+            y = self._vec(x.device)
+        _check(lib().poisson_apply(self.h, _tptr(x), _tptr(y), _stream()), "poisson_apply")
+        return y
+
+    def precond(self, b, x=None):
+        if x is None:
+            x = self._vec(b.device)
+        _check(lib().poisson_precond(self.h, _tptr(b), _tptr(x), _stream()), "poisson_precond")
+        return x
+
+    def assemble_rhs(self, f, g=None, b=None):
+        if b is None:
+            b = self._vec(f.device)
+        _check(lib().poisson_assemble_rhs(self.h, _tptr(f), _tptr(g) if g is not None else None, _tptr(b),
+                                          _stream()), "poisson_assemble_rhs")
+        return b
+
+    def close(self):
+        if self.h:
+            lib().poisson_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_estimate(nx, ny, nz, n_rows, precision=PREC_FP64) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().poisson_workspace_estimate(nx, ny, nz, ctypes.c_int64(n_rows), precision, ctypes.byref(b)),
+           "poisson_workspace_estimate")
+    return b.value
+
+
+def setup(xf, yf, zf, bodies, **opts):
+    """classify + ghost stencils + solver setup for one problem."""
+    flags, cst = classify(xf, yf, zf, bodies)
+    st = build_ghost_stencils(xf, yf, zf, bodies, flags)
+    sol = Solver(xf, yf, zf, flags, st, **opts)
+    return flags, st, sol, cst
+
+
+# ------------------------------------------------------------------ serving
+class Server:
+    """Persistent continuous-batching solve server (one device)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 16, device: int = 0):
+        self.h = ctypes.c_void_p()
+        o = _ServerOpts(hbm_budget, max_slots, device)
+        _check(lib().poisson_server_create(ctypes.byref(o), ctypes.byref(self.h)), "poisson_server_create")
+
+    def submit(self, xf, yf, zf, bodies, f, opts: Optional[PoissonOpts] = None, **kw) -> int:
+        G = _GridArgs(xf, yf, zf)
+        B = _BodyArgs(bodies)
+        ff = np.ascontiguousarray(f, dtype=np.float64)
+        req = _Request(G.g, ctypes.cast(B.arr, ctypes.POINTER(_Body)), B.n, _dptr(ff),
+                       opts if opts is not None else default_opts(**kw))
+        t = ctypes.c_uint64()
+        _check(lib().poisson_submit(self.h, ctypes.byref(req), ctypes.byref(t)), "poisson_submit")
+        return t.value
+
+    def poll(self, ticket: int, n_unknowns: int = 0):
+        """(rc, state, x or None, stats, times); rc IBM_EAGAIN while unfinished."""
+        x = np.zeros(max(n_unknowns, 1))
+        st = PoissonStats()
+        tm = ReqTimes()
+        state = ctypes.c_int32()
+        rc = lib().poisson_poll(self.h, ctypes.c_uint64(ticket), _dptr(x) if n_unknowns else None,
+                                ctypes.c_int64(n_unknowns), ctypes.byref(st), ctypes.byref(tm), ctypes.byref(state))
+        return rc, state.value, (x if n_unknowns else None), st, tm
+
+    def drain(self):
+        _check(lib().poisson_server_drain(self.h), "poisson_server_drain")
+
+    def close(self):
+        if self.h:
+            lib().poisson_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

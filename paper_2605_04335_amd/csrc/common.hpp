@@ -1,0 +1,134 @@
+// Shared host/device helpers of libibmpoisson (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "ibm_poisson.h"
+
+namespace ibm {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string &msg);
+
+#define IBM_HIP(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            throw ::ibm::Error(IBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_) + " at " +   \
+                                             __FILE__ + ":" + std::to_string(__LINE__));                \
+    } while (0)
+
+#define IBM_REQUIRE(cond, code, msg)                                                                    \
+    do {                                                                                                \
+        if (!(cond)) throw ::ibm::Error((code), (msg));                                                 \
+    } while (0)
+
+#define IBM_LAUNCH_CHECK() IBM_HIP(hipGetLastError())
+
+// Wraps an extern "C" body: converts exceptions into return codes.
+template <class F>
+int32_t guarded(F &&f)
+{
+    try {
+        f();
+        return IBM_OK;
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return IBM_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return IBM_EINVAL;
+    }
+}
+
+// ---------------------------------------------------------------- memory
+// Owning device buffer (hipMalloc / hipFree).
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept
+    {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count)
+    {
+        release();
+        n = count;
+        if (count) {
+            hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+            if (e != hipSuccess) {
+                p = nullptr;
+                n = 0;
+                (void)hipGetLastError();
+                throw Error(IBM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
+                                            hipGetErrorString(e));
+            }
+        }
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+template <class T>
+void upload(DBuf<T> &d, const std::vector<T> &h, hipStream_t s)
+{
+    d.alloc(h.size());
+    if (!h.empty()) IBM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------- grid (host)
+struct HostGrid {
+    int n[3];
+    std::vector<double> f[3];
+};
+
+HostGrid read_grid(const ibm_grid *g);
+
+constexpr uint8_t F_SOLID = IBM_F_SOLID, F_GHOST = IBM_F_GHOST, F_MGHOST = IBM_F_MGHOST, F_PIN = IBM_F_PIN,
+                  F_CUTX = IBM_F_CUTX;
+
+}  // namespace ibm
+
+// Stencil table (device-resident), shared between the geometry and the solver
+// translation units.
+struct ibm_stencils {
+    int n[3] = {0, 0, 0};
+    int64_t N = 0;
+    int64_t ng = 0, nm = 0, nfallback = 0, pin = -1;
+    ibm::DBuf<int32_t> cell;   // [ng + nm] closed ghost cells then membrane ghost cells (sorted)
+    ibm::DBuf<int32_t> col;    // [rows*8]
+    ibm::DBuf<double> w;       // [rows*8]
+    ibm::DBuf<double> sG;      // [rows]
+    ibm::DBuf<double> dlb;     // [rows]
+    ibm::DBuf<uint8_t> rfl;    // [rows]
+    ibm::DBuf<double> geo;     // [rows*12]
+};

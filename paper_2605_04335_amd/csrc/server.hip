@@ -1,0 +1,266 @@
+// Continuous-batching solve server: a persistent scheduler thread admits
+// requests while the number of active solves is below max_slots and their
+// summed device footprints fit the HBM budget (first come, first served; a
+// request larger than the whole budget is refused at once).  Every admitted
+// solve runs on its own worker thread and HIP stream, so solves that arrive
+// while others are on the GPU join them and their kernels overlap on the
+// device; a finished solve returns its slot and memory immediately.  Each
+// solve keeps its multigrid hierarchy resident for its lifetime and is
+// deterministic, so a result does not depend on what else is running.
+
+#include "common.hpp"
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+namespace ibm {
+void classify(const ibm_grid *, const ibm_body *, int, uint8_t *, ibm_class_stats *, hipStream_t);
+void build_stencils(const ibm_grid *, const ibm_body *, int, const uint8_t *, ibm_stencils **, hipStream_t);
+size_t estimate_bytes(int nx, int ny, int nz, long long nrows, int precision);
+}  // namespace ibm
+
+using namespace ibm;
+
+namespace {
+
+struct BodyCopy {
+    int kind;
+    std::vector<double> v;
+    std::vector<int32_t> t;
+};
+
+struct Request {
+    uint64_t id = 0;
+    HostGrid g;
+    std::vector<BodyCopy> bodies;
+    std::vector<double> f;
+    poisson_opts opts;
+    size_t footprint = 0;
+    int state = IBM_REQ_QUEUED;
+    int rc = IBM_OK;
+    std::string err;
+    std::vector<double> x;
+    poisson_stats stats{};
+    poisson_req_times times{};
+};
+
+double now_ms(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct poisson_server {
+    poisson_server_opts o;
+    std::chrono::steady_clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request *> queue;
+    std::map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::thread sched;
+    size_t used = 0;
+    int active = 0;
+    uint64_t next_id = 1;
+    bool stop = false;
+
+    void run_request(Request *r);
+    void schedule();
+};
+
+void poisson_server::run_request(Request *r)
+{
+    int rc = IBM_OK;
+    std::string err;
+    hipStream_t s = nullptr;
+    try {
+        IBM_HIP(hipSetDevice(o.device));
+        IBM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        ibm_grid g{r->g.n[0], r->g.n[1], r->g.n[2], r->g.f[0].data(), r->g.f[1].data(), r->g.f[2].data()};
+        std::vector<ibm_body> bd;
+        for (auto &b : r->bodies)
+            bd.push_back(ibm_body{(int32_t)(b.v.size() / 3), (int32_t)(b.t.size() / 3), b.kind, b.v.data(), b.t.data()});
+        const long long N = (long long)g.nx * g.ny * g.nz;
+        DBuf<uint8_t> flags(N);
+        classify(&g, bd.data(), (int)bd.size(), flags.p, nullptr, s);
+        ibm_stencils *st = nullptr;
+        build_stencils(&g, bd.data(), (int)bd.size(), flags.p, &st, s);
+        std::unique_ptr<ibm_stencils> stg(st);
+        const long long nm = st->nm;
+        poisson_ctx *ctx = nullptr;
+        size_t bytes = 0;
+        int e = poisson_setup(&g, flags.p, st, &r->opts, &bytes, &ctx);
+        if (e) throw Error(e, ibm_last_error());
+        std::unique_ptr<poisson_ctx, void (*)(poisson_ctx *)> cg(ctx, poisson_destroy);
+        stg.reset();
+        flags.release();
+        const long long nt = N + nm;
+        DBuf<double> df(N), dx(nt);
+        IBM_HIP(hipMemcpyAsync(df.p, r->f.data(), N * 8, hipMemcpyHostToDevice, s));
+        rc = poisson_solve(ctx, df.p, nullptr, dx.p, &r->stats, s);
+        if (rc && rc != IBM_ENOCONV) err = ibm_last_error();
+        r->x.resize(nt);
+        IBM_HIP(hipMemcpyAsync(r->x.data(), dx.p, nt * 8, hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+    } catch (const Error &e) {
+        rc = e.code;
+        err = e.what();
+    } catch (const std::exception &e) {
+        rc = IBM_EINVAL;
+        err = e.what();
+    }
+    if (s) (void)hipStreamDestroy(s);
+    std::lock_guard<std::mutex> lk(mu);
+    r->rc = rc;
+    r->err = err;
+    r->stats.status = rc;
+    r->state = rc == IBM_OK || rc == IBM_ENOCONV ? IBM_REQ_DONE : IBM_REQ_FAILED;
+    r->times.done_ms = now_ms(t0);
+    used -= r->footprint;
+    --active;
+    cv.notify_all();
+}
+
+void poisson_server::schedule()
+{
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        cv.wait(lk, [&] {
+            if (stop) return true;
+            if (queue.empty()) return false;
+            Request *h = queue.front();
+            return h->footprint > o.hbm_budget || (active < o.max_slots && used + h->footprint <= o.hbm_budget);
+        });
+        if (stop && queue.empty()) break;
+        if (stop) {  // refuse what is still queued
+            for (Request *r : queue) {
+                r->state = IBM_REQ_FAILED;
+                r->rc = IBM_EAGAIN;
+                r->err = "server stopped";
+            }
+            queue.clear();
+            cv.notify_all();
+            break;
+        }
+        Request *r = queue.front();
+        queue.pop_front();
+        if (r->footprint > o.hbm_budget) {
+            r->state = IBM_REQ_FAILED;
+            r->rc = IBM_ENOMEM;
+            r->err = "request footprint exceeds the HBM budget";
+            r->stats.status = IBM_ENOMEM;
+            r->times.admit_ms = r->times.done_ms = now_ms(t0);
+            cv.notify_all();
+            continue;
+        }
+        used += r->footprint;
+        ++active;
+        r->state = IBM_REQ_RUNNING;
+        r->times.admit_ms = now_ms(t0);
+        std::thread([this, r] { run_request(r); }).detach();
+    }
+}
+
+extern "C" int32_t poisson_server_create(const poisson_server_opts *opts, poisson_server **out)
+{
+    return guarded([&] {
+        IBM_REQUIRE(opts && out && opts->max_slots >= 1 && opts->hbm_budget > 0, IBM_EINVAL, "bad server options");
+        auto *S = new poisson_server();
+        S->o = *opts;
+        S->t0 = std::chrono::steady_clock::now();
+        S->sched = std::thread([S] { S->schedule(); });
+        *out = S;
+    });
+}
+
+extern "C" int32_t poisson_submit(poisson_server *S, const poisson_request *q, uint64_t *ticket)
+{
+    return guarded([&] {
+        IBM_REQUIRE(S && q && ticket && q->f, IBM_EINVAL, "null argument");
+        IBM_REQUIRE(q->n_body >= 0 && (q->n_body == 0 || q->bodies), IBM_EINVAL, "bad body list");
+        auto r = std::make_unique<Request>();
+        r->g = read_grid(&q->grid);
+        for (int b = 0; b < q->n_body; ++b) {
+            const ibm_body &B = q->bodies[b];
+            IBM_REQUIRE(B.vert && B.tri && B.n_vert > 0 && B.n_tri > 0, IBM_EINVAL, "empty body");
+            BodyCopy c;
+            c.kind = B.kind;
+            c.v.assign(B.vert, B.vert + 3 * (size_t)B.n_vert);
+            c.t.assign(B.tri, B.tri + 3 * (size_t)B.n_tri);
+            r->bodies.push_back(std::move(c));
+        }
+        const long long N = (long long)r->g.n[0] * r->g.n[1] * r->g.n[2];
+        r->f.assign(q->f, q->f + N);
+        r->opts = q->opts;
+        // footprint: solver workspace plus classification temporaries, with a
+        // generous bound on the ghost rows (one cell in eight)
+        r->footprint = estimate_bytes(r->g.n[0], r->g.n[1], r->g.n[2], N / 8, q->opts.precision) + (size_t)N +
+                       (size_t)N / 2 + (size_t)16 * N;
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->id = S->next_id++;
+        r->times.submit_ms = now_ms(S->t0);
+        *ticket = r->id;
+        S->queue.push_back(r.get());
+        S->reqs[r->id] = std::move(r);
+        S->cv.notify_all();
+    });
+}
+
+extern "C" int32_t poisson_poll(poisson_server *S, uint64_t ticket, double *x_out, int64_t x_len,
+                                poisson_stats *stats, poisson_req_times *times, int32_t *state)
+{
+    int rc = IBM_OK;
+    int32_t g = guarded([&] {
+        IBM_REQUIRE(S, IBM_EINVAL, "null server");
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->reqs.find(ticket);
+        if (it == S->reqs.end()) throw Error(IBM_ENOTFOUND, "unknown ticket");
+        Request *r = it->second.get();
+        if (state) *state = r->state;
+        if (times) *times = r->times;
+        if (r->state == IBM_REQ_QUEUED || r->state == IBM_REQ_RUNNING) { rc = IBM_EAGAIN; return; }
+        if (stats) *stats = r->stats;
+        if (x_out && !r->x.empty()) {
+            IBM_REQUIRE(x_len >= (int64_t)r->x.size(), IBM_EINVAL, "x_out too short");
+            std::copy(r->x.begin(), r->x.end(), x_out);
+        }
+        rc = r->rc;
+        std::string err = r->err;
+        S->reqs.erase(it);
+        if (rc) throw Error(rc, err);
+    });
+    if (g) return g;
+    return rc;
+}
+
+extern "C" int32_t poisson_server_drain(poisson_server *S)
+{
+    return guarded([&] {
+        IBM_REQUIRE(S, IBM_EINVAL, "null server");
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv.wait(lk, [&] { return S->queue.empty() && S->active == 0; });
+    });
+}
+
+extern "C" void poisson_server_destroy(poisson_server *S)
+{
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv.notify_all();
+    }
+    if (S->sched.joinable()) S->sched.join();
+    {
+        // detached workers finish their solve before the server goes away
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv.wait(lk, [&] { return S->active == 0; });
+    }
+    delete S;
+}
