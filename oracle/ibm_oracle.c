@@ -616,6 +616,39 @@ static inline double nbval(const Sys *S, const double *x, int64_t p, int64_t q, 
     return x[q];
 }
 
+/* Inside the smoother a cell next to a cut link sees its neighbour's ghost
+ * unknown eliminated: the current value of that ghost row's stencil,
+ * sum w x - b/sG, instead of the stored unknown (Gauss-Seidel on the system
+ * with the membrane ghost unknowns substituted). */
+static inline double nbval_elim(const Sys *S, const double *x, const double *b, int64_t p, int64_t q, int d, int plus)
+{
+    int64_t lo = plus ? p : q;
+    if (S->flags[lo] & (F_CUTX << d)) {
+        int32_t r = S->ng + S->mg_of[q];
+        double acc = 0.0;
+        for (int m = 0; m < 8; ++m) {
+            int32_t c = S->col[8 * r + m];
+            if (c >= 0) acc += S->w[8 * r + m] * x[c];
+        }
+        return acc - b[S->N + S->mg_of[q]] / S->sG[r];
+    }
+    return x[q];
+}
+
+/* sum c * neighbour over the faces of a fluid cell, with eliminated ghosts */
+static double fluid_offsum_elim(const Sys *S, const double *x, const double *b, int i, int j, int k, int64_t p)
+{
+    const Grid *g = &S->g;
+    int ci[3] = {i, j, k};
+    int64_t st[3] = {1, g->n[0], (int64_t)g->n[0] * g->n[1]};
+    double acc = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        if (ci[d] + 1 < g->n[d]) acc += g->cp[d][ci[d]] * nbval_elim(S, x, b, p, p + st[d], d, 1);
+        if (ci[d] > 0) acc += g->cm[d][ci[d]] * nbval_elim(S, x, b, p, p - st[d], d, 0);
+    }
+    return acc;
+}
+
 /* (A x) for one fluid (non-pin) cell */
 static double fluid_row(const Sys *S, const double *x, int i, int j, int k, int64_t p)
 {
@@ -926,7 +959,13 @@ static void coarse_sweep(const Level *L, double *x, const double *b, int color)
             }
 }
 
-/* level-0 smoothing step: red, black, then Jacobi on all ghost unknowns */
+/* Jacobi on every ghost unknown (closed ghosts and membrane ghost
+ * unknowns), all rows reading the same iterate */
+static void ghost_jacobi(MG *M, double *x, const double *b);
+
+/* level-0 smoothing step: for each colour (red = (i+j+k) even, then black) a
+ * Gauss-Seidel half-sweep over the fluid cells, then Jacobi on all ghost
+ * unknowns */
 static void fine_smooth(MG *M, double *x, const double *b)
 {
     const Sys *S = M->S;
@@ -943,11 +982,15 @@ static void fine_smooth(MG *M, double *x, const double *b)
                     if (f & F_SOLID) continue;
                     double s = cell_scale(g, i, j, k);
                     /* fluid row: sum c (nb - xp) = b  =>  xp = (sum c nb - b) / s */
-                    double r = fluid_row(S, x, i, j, k, p); /* = sum c nb - s xp */
-                    double off = r + s * x[p];
-                    x[p] = (off - b[p]) / s;
+                    x[p] = (fluid_offsum_elim(S, x, b, i, j, k, p) - b[p]) / s;
                 }
+        ghost_jacobi(M, x, b);
     }
+}
+
+static void ghost_jacobi(MG *M, double *x, const double *b)
+{
+    const Sys *S = M->S;
     int32_t nr = S->ng + S->nm;
 #pragma omp parallel for
     for (int32_t r = 0; r < nr; ++r) {
