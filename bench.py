@@ -147,9 +147,9 @@ def main():
     if cnt:
         avg_ms = tot / cnt
         T = 4  # FP32 inner vectors
-        # red/black half-sweep: other-colour neighbours, this colour's RHS, write this colour (T each per
-        # half of the cells) and the flag byte of every cell
-        bytes_launch = (1.5 * T + 1.0) * N
+        # red/black half-sweep over half of the cells: read the other colour's values, this colour's RHS and
+        # flag byte, write this colour's values
+        bytes_launch = (1.5 * T + 0.5) * N
         ach = bytes_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k0_sweep<float>",

@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(TPB) k0_sparse(Lv L, Sp S, const T *x, T *y, c
 // pin slot; coarse - the level mean subtracted from every active RHS.
 template <bool FINE, class T, class TB, int ZMODE>
 __global__ void __launch_bounds__(TPB) k_sweep(Lv L, Geo G, long long pin, T *x, const TB *b, const double *bsh,
-                                               int c)
+                                               int c, int zero_other = 0)
 {
     int h, j, k0, k1;
     if (!geo_tile(G, h, j, k0, k1)) return;
@@ -410,6 +410,9 @@ __global__ void __launch_bounds__(TPB) k_sweep(Lv L, Geo G, long long pin, T *x,
     const TB *bc = b + (long long)c * L.Nh;
     for (int k = k0; k < k1; ++k) {
         const long long s = h + (long long)L.H * (j + (long long)L.ny * k);
+        // from zero with membrane rows: the other colour must read as zero
+        // before its own sweep (membrane rows of this colour read it)
+        if (ZMODE == 1 && zero_other) st(x + (long long)(1 - c) * L.Nh, s, 0.0);
         const uint8_t f = fc[s];
         const int i = 2 * h + ((c + j + k) & 1);
         const bool skip = FINE ? (f & (F_SOLID | F_MGHOST)) != 0 : !(f & 1);
@@ -430,17 +433,35 @@ __global__ void __launch_bounds__(TPB) k_sweep(Lv L, Geo G, long long pin, T *x,
     }
 }
 
-// membrane-adjacent cells of one colour (after the dense half-sweep)
+// membrane-adjacent cells of one colour (after the dense half-sweep): across
+// a cut link the neighbour's ghost unknown is eliminated, i.e. replaced by
+// the current value of its stencil, sum w x - b/sG
 template <class T>
 __global__ void __launch_bounds__(TPB) k0_msweep(Lv L, Sp S, T *x, const T *b, int color)
 {
     for (int m = blockIdx.x * TPB + threadIdx.x; m < S.nm; m += gridDim.x * TPB) {
         if (S.mcolor[m] != color) continue;
         const long long u = S.mslot[m];
-        const double xp = ld(x, u);
-        double s;
-        const double r = mrow(L, S, x, m, xp, s);
-        st(x, u, (r + s * xp - ld(b, u)) / s);
+        int c, h, j, k, i;
+        decode_slot(L, u, c, h, j, k, i);
+        const int32_t *mc = S.mcol + 6 * m;
+        const double cf[6] = {L.cm[0][i], L.cp[0][i], L.cm[1][j], L.cp[1][j], L.cm[2][k], L.cp[2][k]};
+        double off = 0.0, s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int32_t col = mc[q];
+            if (col < 0) continue;
+            double v;
+            if (col >= S.N2) {
+                const int r = S.ng + (int)(col - S.N2);
+                v = ghost_sum(S, x, r) - ld(b, col) / S.rsG[r];
+            } else {
+                v = ld(x, col);
+            }
+            off += cf[q] * v;
+            s += cf[q];
+        }
+        st(x, u, (off - ld(b, u)) / s);
     }
 }
 

@@ -1,0 +1,1037 @@
+// PPE solver (Sec. 2.1: BiCGStab on the pressure Poisson equation; Sec. 2.5
+// module 3: matrix-free bulk plus ELLPACK rows for the irregular part) with a
+// geometric-multigrid V-cycle as right preconditioner, FP64 or mixed
+// precision (FP32 inner BiCGSTAB and V-cycle, BF16 coarse right-hand sides,
+// FP64 iterative refinement).
+//
+// Pinned system: the singular Neumann operator has its first fluid
+// non-membrane-ghost cell's row replaced by -s x = 0.  The preconditioner is
+// V-cycle(b') with b' = b minus the volume-weighted net of b placed at the
+// pin as a sink, run on the unpinned operator, followed by a shift of its
+// output to a zero pin value; the shift is folded into the consumers (the
+// operator writes 0 on the pin row, the x update subtracts the pin values).
+//
+// All vectors are held in the red/black split layout (kernels.hpp); the C
+// ABI takes and returns natural x-fastest arrays, converted at the boundary.
+
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <type_traits>
+
+namespace ibm {
+namespace {
+
+constexpr int PSTRIDE = 16384 + 2048;  // partial slots per reduction: stencil or walk blocks, then sparse blocks
+constexpr int XB = 1024;               // cap on blocks of the sparse row kernels
+
+inline int sparse_blocks(long long n) { return (int)std::max<long long>(1, std::min<long long>(XB, (n + TPB - 1) / TPB)); }
+
+struct Level {
+    int n[3] = {0, 0, 0};
+    int H = 0;
+    long long N = 0, Nh = 0;
+    DBuf<double> cp[3], cm[3], w[3];
+    DBuf<uint8_t> m;                 // split layout: coarse mask (bit0 active, bits1-3 open); level 0 flags
+    DBuf<int> pi[3];                 // prolongation map from the coarse parent
+    DBuf<double> pt[3];
+    double volA = 0.0;               // volume of the active cells
+    Geo geo;
+    Walk walk;                       // over 2 Nh slots
+    DBuf<double> x64, b64;
+    DBuf<float> x32;
+    DBuf<bf16> b16;
+    Lv lv;
+    PMap pm;
+    std::vector<double> hc[3], hw[3];
+    std::vector<uint8_t> hm;         // natural-layout host mask during setup
+};
+
+void level_geometry(Level &L, const std::vector<double> *f, hipStream_t s)
+{
+    for (int d = 0; d < 3; ++d) {
+        int n = L.n[d];
+        L.hc[d].resize(n);
+        L.hw[d].resize(n);
+        std::vector<double> cp(n), cm(n);
+        for (int i = 0; i < n; ++i) {
+            L.hc[d][i] = 0.5 * (f[d][i] + f[d][i + 1]);
+            L.hw[d][i] = f[d][i + 1] - f[d][i];
+        }
+        for (int i = 0; i < n; ++i) {
+            cp[i] = (i + 1 < n) ? 1.0 / (L.hw[d][i] * (L.hc[d][i + 1] - L.hc[d][i])) : 0.0;
+            cm[i] = (i > 0) ? 1.0 / (L.hw[d][i] * (L.hc[d][i] - L.hc[d][i - 1])) : 0.0;
+        }
+        upload(L.cp[d], cp, s);
+        upload(L.cm[d], cm, s);
+        upload(L.w[d], L.hw[d], s);
+    }
+    L.N = (long long)L.n[0] * L.n[1] * L.n[2];
+    L.H = (L.n[0] + 1) / 2;
+    L.Nh = (long long)L.H * L.n[1] * L.n[2];
+    L.geo = make_geo(L.H, L.n[1], L.n[2]);
+    L.walk = make_walk(2 * L.Nh);
+}
+
+// slot of natural cell (i,j,k) in a level with half-width H
+inline long long host_slot(int H, int ny, long long Nh, int i, int j, int k)
+{
+    return (long long)((i + j + k) & 1) * Nh + (i >> 1) + (long long)H * (j + (long long)ny * k);
+}
+
+}  // namespace
+}  // namespace ibm
+
+using namespace ibm;
+
+struct poisson_ctx {
+    poisson_opts opts;
+    HostGrid g;
+    long long N = 0, nm = 0, ng = 0, nrows = 0, n_fallback = 0, pin = 0;
+    long long N2 = 0, Nt = 0;  // 2 Nh cell slots, + membrane unknowns
+    double vol_fluid = 0.0, vol_pin = 0.0;
+    int tail0 = 1;             // first level of the single-workgroup tail
+    DBuf<int32_t> rslot, rcol, mslot, mcol, mcolor;
+    DBuf<double> rw, rsG, rdlb;
+    std::vector<Level> lv;
+    Sp sp;
+    Walk W0;   // over Nt unknowns
+    Walk Wc;   // over 2 Nh cell slots
+    DBuf<double> x, r, rh, p, v, ph, sh, t, rsp, b;
+    DBuf<float> fd, fr, frh, fp, fv, fph, fsh, ft, frsp;
+    DBuf<double> gtmp, sc, part;
+    double *hsc = nullptr;
+    hipStream_t cs = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, ej = nullptr;
+    hipGraphExec_t g64 = nullptr, g32 = nullptr;
+    size_t bytes = 0;
+    bool mixed = false;
+    // per-launch timing of one kernel (HIP events on the solve stream)
+    int prof_kernel = -1;
+    bool capturing = false;
+    std::vector<hipEvent_t> prof_ev;
+    int prof_used = 0;
+    double prof_ms = 0.0;
+    long long prof_count = 0;
+
+    const Lv &L0() const { return lv[0].lv; }
+
+    ~poisson_ctx()
+    {
+        if (g64) (void)hipGraphExecDestroy(g64);
+        if (g32) (void)hipGraphExecDestroy(g32);
+        if (hsc) (void)hipHostFree(hsc);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (ej) (void)hipEventDestroy(ej);
+        if (cs) (void)hipStreamDestroy(cs);
+        for (auto e : prof_ev) (void)hipEventDestroy(e);
+    }
+};
+
+namespace ibm {
+namespace {
+
+// IBM_LOG=1 logs each solve's refinement steps to stderr, IBM_LOG=2 every iteration
+int log_level()
+{
+    static const int lvl = [] {
+        const char *e = getenv("IBM_LOG");
+        return (e && *e) ? atoi(e) : 0;
+    }();
+    return lvl;
+}
+inline bool log_enabled() { return log_level() > 0; }
+
+// kernel ids of the timing hook
+enum { PK_SWEEP0 = 0, PK_APPLY0 = 1, PK_XR = 2 };
+
+inline void prof_begin(poisson_ctx &c, int kid, hipStream_t s)
+{
+    if (c.prof_kernel != kid || c.capturing) return;
+    if ((int)c.prof_ev.size() < 2 * (c.prof_used + 1)) {
+        hipEvent_t a, b;
+        IBM_HIP(hipEventCreate(&a));
+        IBM_HIP(hipEventCreate(&b));
+        c.prof_ev.push_back(a);
+        c.prof_ev.push_back(b);
+    }
+    IBM_HIP(hipEventRecord(c.prof_ev[2 * c.prof_used], s));
+}
+
+inline void prof_end(poisson_ctx &c, int kid, hipStream_t s)
+{
+    if (c.prof_kernel != kid || c.capturing) return;
+    IBM_HIP(hipEventRecord(c.prof_ev[2 * c.prof_used + 1], s));
+    ++c.prof_used;
+}
+
+inline void prof_harvest(poisson_ctx &c)
+{
+    for (int i = 0; i < c.prof_used; ++i) {
+        float ms = 0.f;
+        IBM_HIP(hipEventElapsedTime(&ms, c.prof_ev[2 * i], c.prof_ev[2 * i + 1]));
+        c.prof_ms += ms;
+        ++c.prof_count;
+    }
+    c.prof_used = 0;
+}
+
+inline void fin(poisson_ctx &c, int n, int op, int dst, double aux, hipStream_t s)
+{
+    k_fin<<<1, 1024, 0, s>>>(c.part.p, PSTRIDE, n, op, dst, aux, c.sc.p);
+    IBM_LAUNCH_CHECK();
+}
+
+// y = A x (or y = b - A x) on level 0, with dots; returns the partial count
+template <class T>
+int launch_apply(poisson_ctx &c, int mode, bool res, int nd, const T *x, T *y, const T *b, const double *sink,
+                 const T *u1, const T *u2, hipStream_t s)
+{
+    const Level &L = c.lv[0];
+    double *P = c.part.p;
+    const int nsp = (int)(c.nrows + c.nm);
+    const int sb = sparse_blocks(nsp);
+    const int gb = L.geo.nb;
+#define AP(MODE, RES, ND)                                                                                        \
+    k0_apply<T, MODE, RES, ND><<<gb, TPB, 0, s>>>(L.lv, L.geo, c.pin, x, y, b, sink, u1, u2, P, PSTRIDE);      \
+    if (nsp) k0_sparse<T, RES, ND><<<sb, TPB, 0, s>>>(L.lv, c.sp, x, y, b, u1, u2, P, PSTRIDE, gb);
+    if (res) {
+        if (mode == M_PINNED && nd == 2) { AP(M_PINNED, true, 2) }
+        else throw Error(IBM_EINVAL, "apply variant");
+    } else {
+        if (mode == M_PINZERO && nd == 1) { AP(M_PINZERO, false, 1) }
+        else if (mode == M_PINZERO && nd == 2) { AP(M_PINZERO, false, 2) }
+        else if (mode == M_PINNED && nd == 0) { AP(M_PINNED, false, 0) }
+        else throw Error(IBM_EINVAL, "apply variant");
+    }
+#undef AP
+    IBM_LAUNCH_CHECK();
+    return gb + (nsp ? sb : 0);
+}
+
+template <class T>
+struct Store;
+template <>
+struct Store<double> {
+    typedef double Tc;
+    typedef double TB;
+    static Tc *x(Level &L) { return L.x64.p; }
+    static TB *b(Level &L) { return L.b64.p; }
+};
+template <>
+struct Store<float> {
+    typedef float Tc;
+    typedef bf16 TB;
+    static Tc *x(Level &L) { return L.x32.p; }
+    static TB *b(Level &L) { return L.b16.p; }
+};
+
+// level-0 smoothing step: for red then black, the dense half-sweep, the
+// membrane-adjacent cells of that colour, then Jacobi on all ghost unknowns
+template <class T>
+void fine_smooth(poisson_ctx &c, T *x, const T *b, const double *sink, bool from_zero, hipStream_t s)
+{
+    const Level &L = c.lv[0];
+    const int mb = sparse_blocks(c.nm), gb = sparse_blocks(c.nrows);
+    for (int color = 0; color < 2; ++color) {
+        if (from_zero && color == 0) {
+            k_sweep<true, T, T, 1><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, c.pin, x, b, sink, 0, c.nm > 0 ? 1 : 0);
+            if (c.nm) {
+                Walk Wt = make_walk(c.nm);
+                k_fill<T><<<Wt.nb, TPB, 0, s>>>(Wt, x + c.N2, 0.0);
+            }
+        } else if (from_zero) {
+            k_sweep<true, T, T, 2><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, c.pin, x, b, sink, 1);
+        } else {
+            prof_begin(c, PK_SWEEP0, s);
+            k_sweep<true, T, T, 0><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, c.pin, x, b, sink, color);
+            prof_end(c, PK_SWEEP0, s);
+        }
+        if (c.nm) k0_msweep<T><<<mb, TPB, 0, s>>>(L.lv, c.sp, x, b, color);
+        if (c.nrows) {
+            k0_gjac<T><<<gb, TPB, 0, s>>>(c.sp, x, b, c.gtmp.p);
+            k0_gscat<T><<<gb, TPB, 0, s>>>(c.sp, x, c.gtmp.p);
+        }
+    }
+    IBM_LAUNCH_CHECK();
+}
+
+template <class Tc, class TB>
+void coarse_smooth(Level &L, int steps, bool from_zero, const double *mean, hipStream_t s)
+{
+    Tc *x = Store<Tc>::x(L);
+    const TB *b = Store<Tc>::b(L);
+    for (int it = 0; it < steps; ++it) {
+        if (it == 0 && from_zero) {
+            k_sweep<false, Tc, TB, 1><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, -1, x, b, mean, 0);
+            k_sweep<false, Tc, TB, 2><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, -1, x, b, mean, 1);
+        } else {
+            k_sweep<false, Tc, TB, 0><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, -1, x, b, mean, 0);
+            k_sweep<false, Tc, TB, 0><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, -1, x, b, mean, 1);
+        }
+    }
+    IBM_LAUNCH_CHECK();
+}
+
+// x = V-cycle(b) on the unpinned operator with the sink at the pin; x unshifted
+template <class T>
+void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
+{
+    typedef typename Store<T>::Tc Tc;
+    typedef typename Store<T>::TB TB;
+    const int nl = (int)c.lv.size();
+    const poisson_opts &o = c.opts;
+    for (int it = 0; it < o.nu1; ++it) fine_smooth<T>(c, x, b, sink, it == 0, s);
+    if (nl > 1) {
+        T *rsp = std::is_same<T, double>::value ? (T *)c.rsp.p : (T *)c.frsp.p;
+        const int nsp = (int)(c.nrows + c.nm);
+        if (nsp) k0_sparse_res<T><<<sparse_blocks(nsp), TPB, 0, s>>>(c.lv[0].lv, c.sp, x, b, rsp);
+        Level &L1 = c.lv[1];
+        k_restrict<true, T, T, TB><<<L1.geo.nb, TPB, 0, s>>>(c.lv[0].lv, L1.lv, L1.geo, c.pin, x, b, sink, rsp,
+                                                            Store<T>::b(L1), c.part.p);
+        IBM_LAUNCH_CHECK();
+        fin(c, L1.geo.nb, FIN_MEAN, S_MEAN0 + 1, L1.volA, s);
+        const int lt = c.tail0;
+        for (int l = 1; l < lt; ++l) {
+            Level &L = c.lv[l];
+            const double *mean = c.sc.p + S_MEAN0 + l;
+            if (l == nl - 1) {
+                coarse_smooth<Tc, TB>(L, o.coarse_sweeps, true, mean, s);
+                break;
+            }
+            coarse_smooth<Tc, TB>(L, o.nu1, true, mean, s);
+            Level &C = c.lv[l + 1];
+            k_restrict<false, Tc, TB, TB><<<C.geo.nb, TPB, 0, s>>>(L.lv, C.lv, C.geo, -1, Store<T>::x(L),
+                                                                  Store<T>::b(L), mean, (const Tc *)nullptr,
+                                                                  Store<T>::b(C), c.part.p);
+            IBM_LAUNCH_CHECK();
+            fin(c, C.geo.nb, FIN_MEAN, S_MEAN0 + l + 1, C.volA, s);
+        }
+        if (lt < nl) {
+            Tail tl;
+            tl.n = nl - lt;
+            tl.nu1 = o.nu1;
+            tl.nu2 = o.nu2;
+            tl.ncs = o.coarse_sweeps;
+            for (int q = 0; q < tl.n; ++q) {
+                Level &L = c.lv[lt + q];
+                tl.t[q].L = L.lv;
+                tl.t[q].M = L.pm;
+                tl.t[q].volA = L.volA;
+                tl.t[q].x = Store<T>::x(L);
+                tl.t[q].b = Store<T>::b(L);
+                tl.t[q].r = nullptr;
+            }
+            k_tail<Tc, TB><<<1, TAIL_T, 0, s>>>(tl, c.sc.p + S_MEAN0 + lt);
+            IBM_LAUNCH_CHECK();
+        }
+        for (int l = std::min(lt, nl - 1) - 1; l >= 1; --l) {
+            Level &L = c.lv[l];
+            Level &C = c.lv[l + 1];
+            k_prolong<false, Tc, Tc><<<L.geo.nb, TPB, 0, s>>>(L.lv, C.lv, L.pm, L.geo, Store<T>::x(C), Store<T>::x(L));
+            coarse_smooth<Tc, TB>(L, o.nu2, false, c.sc.p + S_MEAN0 + l, s);
+        }
+        Level &L0v = c.lv[0];
+        k_prolong<true, Tc, T><<<L0v.geo.nb, TPB, 0, s>>>(L0v.lv, L1.lv, L0v.pm, L0v.geo, Store<T>::x(L1), x);
+        IBM_LAUNCH_CHECK();
+    }
+    for (int it = 0; it < o.nu2; ++it) fine_smooth<T>(c, x, b, sink, false, s);
+}
+
+// One BiCGSTAB iteration (van der Vorst 1992, right preconditioning): all
+// scalars stay on the device.
+template <class T>
+void bicg_iteration(poisson_ctx &c, T *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, hipStream_t s)
+{
+    const Walk &W = c.W0;
+    const Lv &L = c.L0();
+    k_p_update<T><<<W.nb, TPB, 0, s>>>(L, W, r, p, v, c.sc.p, c.part.p);
+    fin(c, W.nb, FIN_SINK, S_SINKP, 0.0, s);
+    vcycle<T>(c, p, ph, c.sc.p + S_SINKP, s);
+    prof_begin(c, PK_APPLY0, s);
+    int np = launch_apply<T>(c, M_PINZERO, false, 1, ph, v, nullptr, nullptr, rh, nullptr, s);
+    prof_end(c, PK_APPLY0, s);
+    fin(c, np, FIN_ALPHA, 0, 0.0, s);
+    k_s_update<T><<<W.nb, TPB, 0, s>>>(L, W, r, v, c.sc.p, c.part.p);
+    fin(c, W.nb, FIN_SINK, S_SINKS, 0.0, s);
+    vcycle<T>(c, r, sh, c.sc.p + S_SINKS, s);
+    np = launch_apply<T>(c, M_PINZERO, false, 2, sh, t, nullptr, nullptr, r, nullptr, s);
+    fin(c, np, FIN_OMEGA, 0, 0.0, s);
+    prof_begin(c, PK_XR, s);
+    k_xr_update<T, T><<<W.nb, TPB, 0, s>>>(L, W, c.pin, y, ph, sh, r, t, rh, c.sc.p, c.part.p, PSTRIDE);
+    prof_end(c, PK_XR, s);
+    IBM_LAUNCH_CHECK();
+    fin(c, W.nb, FIN_RHO, 0, 0.0, s);
+}
+
+void read_scalars(poisson_ctx &c, hipStream_t s)
+{
+    IBM_HIP(hipMemcpyAsync(c.hsc, c.sc.p, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    prof_harvest(c);
+}
+
+// Right-preconditioned BiCGSTAB on A y = rhs; y starts at zero.  Returns the
+// iteration count; *rc gets the status.
+template <class T>
+int bicgstab(poisson_ctx &c, const T *rhs, T *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, double tol, int maxit,
+             bool true_check, hipGraphExec_t *graph, hipStream_t s, int *rc, double *relout)
+{
+    const Walk &W = c.W0;
+    k_fill<T><<<W.nb, TPB, 0, s>>>(W, y, 0.0);
+    k_fill<T><<<W.nb, TPB, 0, s>>>(W, p, 0.0);
+    k_fill<T><<<W.nb, TPB, 0, s>>>(W, v, 0.0);
+    k_copy_norm<T, T><<<W.nb, TPB, 0, s>>>(W, rhs, r, rh, c.part.p);
+    IBM_LAUNCH_CHECK();
+    fin(c, W.nb, FIN_INIT, 0, 0.0, s);
+    read_scalars(c, s);
+    *rc = IBM_ENOCONV;
+    if (c.hsc[S_BN2] == 0.0) {
+        *rc = IBM_OK;
+        *relout = 0.0;
+        return 0;
+    }
+    const bool use_graph = c.opts.use_graph && c.prof_kernel < 0;
+    if (use_graph && !*graph) {
+        hipGraph_t gr;
+        c.capturing = true;
+        IBM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        bicg_iteration<T>(c, y, r, rh, p, v, ph, sh, t, s);
+        IBM_HIP(hipStreamEndCapture(s, &gr));
+        c.capturing = false;
+        IBM_HIP(hipGraphInstantiate(graph, gr, nullptr, nullptr, 0));
+        IBM_HIP(hipGraphDestroy(gr));
+    }
+    int it = 0;
+    double rel = 1.0;
+    while (it < maxit) {
+        ++it;
+        if (use_graph) IBM_HIP(hipGraphLaunch(*graph, s));
+        else bicg_iteration<T>(c, y, r, rh, p, v, ph, sh, t, s);
+        read_scalars(c, s);
+        const double st = c.hsc[S_STATUS];
+        rel = c.hsc[S_REL];
+        if (log_level() >= 2)
+            fprintf(stderr, "[ibm]   it %d rel %.3e status %g\n", it, rel, st);
+        if (st >= 2.0 || !std::isfinite(rel)) { *rc = IBM_EBREAKDOWN; break; }
+        if (rel <= tol) {
+            if (!true_check) { *rc = IBM_OK; break; }
+            int np = launch_apply<T>(c, M_PINNED, true, 2, y, t, rhs, nullptr, rh, nullptr, s);
+            k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
+            read_scalars(c, s);
+            double trel = std::sqrt(c.hsc[S_TMP] / c.hsc[S_BN2]);
+            rel = trel;
+            if (trel <= tol) { *rc = IBM_OK; break; }
+            // residual replacement
+            k_copy<T, T><<<W.nb, TPB, 0, s>>>(W, t, r);
+            k_dot2<T><<<W.nb, TPB, 0, s>>>(W, rh, r, c.part.p, PSTRIDE);
+            fin(c, W.nb, FIN_REPLACE, 0, 0.0, s);
+            continue;
+        }
+        if (st == 1.0) {  // rho breakdown: restart with rh = r
+            k_fill<T><<<W.nb, TPB, 0, s>>>(W, p, 0.0);
+            k_fill<T><<<W.nb, TPB, 0, s>>>(W, v, 0.0);
+            k_copy_norm<T, T><<<W.nb, TPB, 0, s>>>(W, r, rh, (T *)nullptr, c.part.p);
+            fin(c, W.nb, FIN_RESTART, 0, 0.0, s);
+        }
+    }
+    *relout = rel;
+    return it;
+}
+
+// ------------------------------------------------------------------ RHS, gauge (split layout)
+__global__ void __launch_bounds__(TPB) k_rhs(Lv L, Walk W, long long pin, const double *fs, const double *sc,
+                                             int slot_, double *b)
+{
+    const double mean = sc[slot_];
+    WALK_BEGIN(W, p)
+        if (p >= 2 * L.Nh) { b[p] = 0.0; continue; }
+        const uint8_t fl = L.f[p];
+        b[p] = ((fl & F_SOLID) || p == pin) ? 0.0 : fs[p] - mean;
+    WALK_END
+}
+
+__global__ void __launch_bounds__(TPB) k_rhs_ghost(Sp S, const double *dlb, const double *g, double *b)
+{
+    for (int r = blockIdx.x * TPB + threadIdx.x; r < S.nrows; r += gridDim.x * TPB)
+        b[ghost_unknown(S, r)] = g ? S.rsG[r] * dlb[r] * g[r] : 0.0;
+}
+
+__global__ void __launch_bounds__(TPB) k_gauge(Lv L, Walk W, const double *x, const double *sc, int slot_, double *out)
+{
+    const double mean = sc[slot_];
+    WALK_BEGIN(W, p)
+        const bool act = p >= 2 * L.Nh || active0(L.f[p]);
+        out[p] = act ? x[p] - mean : 0.0;
+    WALK_END
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k_shift(Lv L, Walk W, long long pin, T *x)
+{
+    const double c = ld(x, pin);
+    WALK_BEGIN(W, p)
+        if (p != pin && (p >= 2 * L.Nh || active0(L.f[p]))) st(x, p, ld(x, p) - c);
+    WALK_END
+}
+
+__global__ void k_shift_pin(long long pin, double *x) { x[pin] = 0.0; }
+
+// unpinned residual at the pin (the inconsistency the pin absorbs)
+__global__ void k_pinres(Lv L, long long pin, const double *x, double *sc)
+{
+    if (threadIdx.x || blockIdx.x) return;
+    int c, h, j, k, i;
+    decode_slot(L, pin, c, h, j, k, i);
+    double dg;
+    const double off = nbsum<true>(L, x + (long long)(1 - c) * L.Nh, L.f + (long long)(1 - c) * L.Nh, h, j, k, i,
+                                   L.f[pin], dg);
+    sc[S_TMP] = off - dg * x[pin];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ setup
+size_t estimate_bytes(int nx, int ny, int nz, long long nrows, int precision)
+{
+    long long Nh = (long long)((nx + 1) / 2) * ny * nz;
+    long long Nt = 2 * Nh + nrows;
+    size_t b = (size_t)2 * Nh;  // flags
+    b += (size_t)nrows * (8 * 4 + 8 * 8 + 16 + 8 + 4 + 6 * 4 + 4);
+    b += (size_t)Nt * 8 * (precision == IBM_PREC_MIXED ? 4 : 10);
+    if (precision == IBM_PREC_MIXED) b += (size_t)Nt * 4 * 9;
+    long long Nc = 2 * Nh;
+    size_t coarse = 0;
+    while (true) {
+        Nc /= 8;
+        if (Nc < 8) break;
+        coarse += (size_t)Nc * (precision == IBM_PREC_MIXED ? (4 + 2 + 1) : (8 * 2 + 1));
+    }
+    b += coarse;
+    b += (size_t)PSTRIDE * 4 * 8;
+    return b;
+}
+
+poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencils *st, const poisson_opts *opts)
+{
+    IBM_REQUIRE(flags && st, IBM_EINVAL, "null argument");
+    std::unique_ptr<poisson_ctx> c(new poisson_ctx());
+    if (opts) c->opts = *opts; else poisson_default_opts(&c->opts);
+    poisson_opts &o = c->opts;
+    IBM_REQUIRE(o.tol > 0 && o.max_iter > 0 && o.nu1 >= 1 && o.nu2 >= 0 && o.coarse_sweeps >= 1, IBM_EINVAL,
+                "bad solver options");
+    c->mixed = o.precision == IBM_PREC_MIXED;
+    c->g = read_grid(grid);
+    for (int d = 0; d < 3; ++d) IBM_REQUIRE(c->g.n[d] == st->n[d], IBM_EINVAL, "stencil table of another grid");
+    IBM_HIP(hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking));
+    IBM_HIP(hipEventCreate(&c->e0));
+    IBM_HIP(hipEventCreate(&c->e1));
+    IBM_HIP(hipEventCreateWithFlags(&c->ej, hipEventDisableTiming));
+    IBM_HIP(hipHostMalloc((void **)&c->hsc, S_COUNT * sizeof(double), hipHostMallocDefault));
+    hipStream_t s = c->cs;
+    const HostGrid &g = c->g;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const long long N = (long long)nx * ny * nz;
+    c->N = N;
+    c->ng = st->ng;
+    c->nm = st->nm;
+    c->nrows = st->ng + st->nm;
+    c->n_fallback = st->nfallback;
+    // host copies of the classification and the ghost rows
+    std::vector<uint8_t> hf(N);
+    IBM_HIP(hipMemcpyAsync(hf.data(), flags, N, hipMemcpyDeviceToHost, s));
+    const long long R = c->nrows;
+    std::vector<int32_t> hcell(std::max<long long>(R, 1)), hcol(std::max<long long>(R, 1) * 8);
+    if (R) {
+        IBM_HIP(hipMemcpyAsync(hcell.data(), st->cell.p, R * 4, hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipMemcpyAsync(hcol.data(), st->col.p, R * 32, hipMemcpyDeviceToHost, s));
+    }
+    IBM_HIP(hipStreamSynchronize(s));
+    // levels
+    int nl = 1;
+    {
+        int n[3] = {nx, ny, nz};
+        while (nl < 16) {
+            bool even = n[0] % 2 == 0 && n[1] % 2 == 0 && n[2] % 2 == 0;
+            int mn = std::min(n[0], std::min(n[1], n[2]));
+            if (!even || mn <= 4) break;
+            for (int d = 0; d < 3; ++d) n[d] /= 2;
+            ++nl;
+        }
+    }
+    c->lv.resize(nl);
+    std::vector<double> faces[3];
+    for (int d = 0; d < 3; ++d) faces[d] = g.f[d];
+    for (int l = 0; l < nl; ++l) {
+        Level &L = c->lv[l];
+        for (int d = 0; d < 3; ++d) L.n[d] = g.n[d] >> l;
+        if (l > 0)
+            for (int d = 0; d < 3; ++d) {
+                std::vector<double> cf(L.n[d] + 1);
+                for (int i = 0; i <= L.n[d]; ++i) cf[i] = faces[d][2 * i];
+                faces[d] = cf;
+            }
+        level_geometry(L, faces, s);
+    }
+    Level &Z = c->lv[0];
+    c->N2 = 2 * Z.Nh;
+    c->Nt = c->N2 + c->nm;
+    auto slot0 = [&](long long cell) {
+        int i = (int)(cell % nx), j = (int)((cell / nx) % ny), k = (int)(cell / ((long long)nx * ny));
+        return host_slot(Z.H, ny, Z.Nh, i, j, k);
+    };
+    auto unk0 = [&](long long col) { return col < N ? slot0(col) : c->N2 + (col - N); };
+    // level-0 flags in split layout (padding slots are solid)
+    {
+        std::vector<uint8_t> sf(c->N2, F_SOLID);
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    sf[host_slot(Z.H, ny, Z.Nh, i, j, k)] = hf[i + (long long)nx * (j + (long long)ny * k)];
+        upload(Z.m, sf, s);
+    }
+    c->pin = slot0(st->pin);
+    // sparse rows
+    {
+        std::vector<int32_t> rs(std::max<long long>(c->ng, 1)), rc(std::max<long long>(R, 1) * 8, -1);
+        for (long long r = 0; r < c->ng; ++r) rs[r] = (int32_t)slot0(hcell[r]);
+        for (long long q = 0; q < R * 8; ++q) rc[q] = hcol[q] >= 0 ? (int32_t)unk0(hcol[q]) : -1;
+        upload(c->rslot, rs, s);
+        upload(c->rcol, rc, s);
+        const long long RR = std::max<long long>(R, 1);
+        c->rw.alloc(RR * 8); c->rsG.alloc(RR); c->rdlb.alloc(RR);
+        if (R) {
+            IBM_HIP(hipMemcpyAsync(c->rw.p, st->w.p, R * 64, hipMemcpyDeviceToDevice, s));
+            IBM_HIP(hipMemcpyAsync(c->rsG.p, st->sG.p, R * 8, hipMemcpyDeviceToDevice, s));
+            IBM_HIP(hipMemcpyAsync(c->rdlb.p, st->dlb.p, R * 8, hipMemcpyDeviceToDevice, s));
+        }
+        // membrane-adjacent cells: slots, colours, and neighbour unknowns (-x,+x,-y,+y,-z,+z)
+        const long long nm = c->nm;
+        std::vector<int32_t> ms(std::max<long long>(nm, 1)), mc(std::max<long long>(nm, 1) * 6, -1),
+            mk(std::max<long long>(nm, 1));
+        std::vector<int32_t> mcell(hcell.begin() + c->ng, hcell.begin() + c->ng + nm);
+        for (long long m = 0; m < nm; ++m) {
+            long long p = mcell[m];
+            int ci[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / ((long long)nx * ny))};
+            long long strd[3] = {1, nx, (long long)nx * ny};
+            ms[m] = (int32_t)slot0(p);
+            mk[m] = (ci[0] + ci[1] + ci[2]) & 1;
+            for (int d = 0; d < 3; ++d)
+                for (int sg = 0; sg < 2; ++sg) {
+                    int c2 = ci[d] + (sg ? 1 : -1);
+                    if (c2 < 0 || c2 >= g.n[d]) continue;
+                    long long q = p + (sg ? strd[d] : -strd[d]);
+                    long long lo = sg ? p : q;
+                    long long col;
+                    if (hf[lo] & (F_CUTX << d)) {
+                        auto it = std::lower_bound(mcell.begin(), mcell.end(), (int32_t)q);
+                        IBM_REQUIRE(it != mcell.end() && *it == q, IBM_EGEOM, "cut link without ghost");
+                        col = c->N2 + (it - mcell.begin());
+                    } else {
+                        col = slot0(q);
+                    }
+                    mc[6 * m + 2 * d + sg] = (int32_t)col;
+                }
+        }
+        upload(c->mslot, ms, s);
+        upload(c->mcol, mc, s);
+        upload(c->mcolor, mk, s);
+    }
+    // fluid volume, pin volume
+    {
+        double sv = 0.0;
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    if (!(hf[i + (long long)nx * (j + (long long)ny * k)] & F_SOLID))
+                        sv += Z.hw[0][i] * Z.hw[1][j] * Z.hw[2][k];
+        c->vol_fluid = sv;
+        long long p = st->pin;
+        int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((long long)nx * ny));
+        c->vol_pin = Z.hw[0][i] * Z.hw[1][j] * Z.hw[2][k];
+    }
+    // coarse masks: active, cut (propagated), open faces; then split layout
+    for (int l = 1; l < nl; ++l) {
+        Level &F = c->lv[l - 1], &C = c->lv[l];
+        C.hm.assign(C.N, 0);
+        const int fnx = F.n[0], fny = F.n[1];
+        for (int K = 0; K < C.n[2]; ++K)
+            for (int J = 0; J < C.n[1]; ++J)
+                for (int I = 0; I < C.n[0]; ++I) {
+                    uint8_t act = 0, cut = 0;
+                    for (int q = 0; q < 8; ++q) {
+                        int dx = q & 1, dy = (q >> 1) & 1, dz = (q >> 2) & 1;
+                        long long p = (2 * I + dx) + (long long)fnx * ((2 * J + dy) + (long long)fny * (2 * K + dz));
+                        uint8_t a, cb;
+                        if (l == 1) {
+                            uint8_t f = hf[p];
+                            a = (!(f & F_SOLID) || (f & F_GHOST)) ? 1 : 0;
+                            cb = (f >> 4) & 7;
+                        } else {
+                            a = F.hm[p] & 1;
+                            cb = (F.hm[p] >> 4) & 7;
+                        }
+                        act |= a;
+                        if (dx && (cb & 1)) cut |= 16;
+                        if (dy && (cb & 2)) cut |= 32;
+                        if (dz && (cb & 4)) cut |= 64;
+                    }
+                    C.hm[I + (long long)C.n[0] * (J + (long long)C.n[1] * K)] = act | cut;
+                }
+        double va = 0.0;
+        for (int K = 0; K < C.n[2]; ++K)
+            for (int J = 0; J < C.n[1]; ++J)
+                for (int I = 0; I < C.n[0]; ++I) {
+                    long long P = I + (long long)C.n[0] * (J + (long long)C.n[1] * K);
+                    if (!(C.hm[P] & 1)) continue;
+                    va += C.hw[0][I] * C.hw[1][J] * C.hw[2][K];
+                    long long strd[3] = {1, C.n[0], (long long)C.n[0] * C.n[1]};
+                    int ci[3] = {I, J, K};
+                    for (int d = 0; d < 3; ++d)
+                        if (ci[d] + 1 < C.n[d] && (C.hm[P + strd[d]] & 1) && !(C.hm[P] & (16 << d)))
+                            C.hm[P] |= (uint8_t)(2 << d);
+                }
+        C.volA = va;
+        std::vector<uint8_t> sm(2 * C.Nh, 0);
+        for (int K = 0; K < C.n[2]; ++K)
+            for (int J = 0; J < C.n[1]; ++J)
+                for (int I = 0; I < C.n[0]; ++I)
+                    sm[host_slot(C.H, C.n[1], C.Nh, I, J, K)] =
+                        C.hm[I + (long long)C.n[0] * (J + (long long)C.n[1] * K)] & 15;
+        upload(C.m, sm, s);
+        // prolongation maps of F from C
+        for (int d = 0; d < 3; ++d) {
+            int nf = F.n[d], nc = C.n[d];
+            std::vector<int> pi(nf);
+            std::vector<double> pt(nf);
+            for (int i = 0; i < nf; ++i) {
+                double x = F.hc[d][i];
+                x = std::min(std::max(x, C.hc[d][0]), C.hc[d][nc - 1]);
+                int I0 = 0;
+                while (I0 + 1 <= nc - 2 && C.hc[d][I0 + 1] <= x) ++I0;
+                pi[i] = I0;
+                pt[i] = (x - C.hc[d][I0]) / (C.hc[d][I0 + 1] - C.hc[d][I0]);
+            }
+            upload(F.pi[d], pi, s);
+            upload(F.pt[d], pt, s);
+        }
+    }
+    // device views, coarse storage, tail start
+    c->tail0 = nl;
+    for (int l = nl - 1; l >= 1 && c->lv[l].N <= TAIL_MAX && (nl - l) <= 8; --l) c->tail0 = l;
+    for (int l = 0; l < nl; ++l) {
+        Level &L = c->lv[l];
+        Lv &v = L.lv;
+        v.nx = L.n[0]; v.ny = L.n[1]; v.nz = L.n[2]; v.H = L.H; v.Nh = L.Nh;
+        v.fH = make_fdiv(L.H);
+        v.fy = make_fdiv(L.n[1]);
+        for (int d = 0; d < 3; ++d) { v.cp[d] = L.cp[d].p; v.cm[d] = L.cm[d].p; v.w[d] = L.w[d].p; }
+        v.f = L.m.p;
+        for (int d = 0; d < 3; ++d) { L.pm.pi[d] = L.pi[d].p; L.pm.pt[d] = L.pt[d].p; }
+        if (l > 0) {
+            if (c->mixed) { L.x32.alloc(2 * L.Nh); L.b16.alloc(2 * L.Nh); }
+            else { L.x64.alloc(2 * L.Nh); L.b64.alloc(2 * L.Nh); }
+        }
+    }
+    Sp &S = c->sp;
+    S.N2 = c->N2;
+    S.pin = c->pin;
+    S.nrows = (int)c->nrows;
+    S.ng = (int)c->ng;
+    S.rslot = c->rslot.p; S.rcol = c->rcol.p; S.rw = c->rw.p; S.rsG = c->rsG.p;
+    S.nm = (int)c->nm;
+    S.mslot = c->mslot.p; S.mcol = c->mcol.p; S.mcolor = c->mcolor.p;
+    c->W0 = make_walk(c->Nt);
+    c->Wc = make_walk(c->N2);
+    const long long Nt = c->Nt;
+    c->x.alloc(Nt); c->r.alloc(Nt); c->b.alloc(Nt); c->t.alloc(Nt);
+    if (!c->mixed) {
+        c->rh.alloc(Nt); c->p.alloc(Nt); c->v.alloc(Nt); c->ph.alloc(Nt); c->sh.alloc(Nt); c->rsp.alloc(Nt);
+    } else {
+        c->fd.alloc(Nt); c->fr.alloc(Nt); c->frh.alloc(Nt); c->fp.alloc(Nt); c->fv.alloc(Nt);
+        c->fph.alloc(Nt); c->fsh.alloc(Nt); c->ft.alloc(Nt); c->frsp.alloc(Nt);
+    }
+    c->gtmp.alloc(std::max<long long>(R, 1));
+    c->sc.alloc(S_COUNT);
+    c->part.alloc((size_t)PSTRIDE * 4);
+    std::vector<double> sc0(S_COUNT, 0.0);
+    sc0[S_VPIN] = c->vol_pin;
+    IBM_HIP(hipMemcpyAsync(c->sc.p, sc0.data(), S_COUNT * 8, hipMemcpyHostToDevice, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    c->bytes = estimate_bytes(nx, ny, nz, c->nrows, o.precision);
+    for (auto &L : c->lv) { L.hm.clear(); L.hm.shrink_to_fit(); }
+    IBM_REQUIRE(c->lv[0].geo.nb <= PSTRIDE - 2048 && c->W0.nb <= PSTRIDE - 2048, IBM_EINVAL, "grid too large");
+    for (auto &L : c->lv) IBM_REQUIRE(L.geo.nb <= PSTRIDE, IBM_EINVAL, "grid too large");
+    return c.release();
+}
+
+// ------------------------------------------------------------------ solve
+struct StreamJoin {
+    poisson_ctx &c;
+    hipStream_t user;
+    StreamJoin(poisson_ctx &cc, hipStream_t u) : c(cc), user(u)
+    {
+        IBM_HIP(hipEventRecord(c.ej, user));
+        IBM_HIP(hipStreamWaitEvent(c.cs, c.ej, 0));
+    }
+    ~StreamJoin()
+    {
+        (void)hipEventRecord(c.ej, c.cs);
+        (void)hipStreamWaitEvent(user, c.ej, 0);
+    }
+};
+
+namespace {
+
+void to_split(poisson_ctx &c, const double *nat, double *spl, long long tail, hipStream_t s)
+{
+    k_to_split<double, double><<<c.W0.nb, TPB, 0, s>>>(c.L0(), c.W0, nat, spl, tail);
+    IBM_LAUNCH_CHECK();
+}
+
+void from_split(poisson_ctx &c, const double *spl, double *nat, long long tail, hipStream_t s)
+{
+    k_from_split<double, double><<<c.W0.nb, TPB, 0, s>>>(c.L0(), c.W0, spl, nat, tail);
+    IBM_LAUNCH_CHECK();
+}
+
+// b (split) from raw natural f and optional g
+void assemble_rhs(poisson_ctx &c, const double *f, const double *gval, double *b, hipStream_t s)
+{
+    to_split(c, f, c.t.p, 0, s);
+    k_vsum<double, false><<<c.Wc.nb, TPB, 0, s>>>(c.L0(), c.Wc, c.t.p, c.part.p);
+    fin(c, c.Wc.nb, FIN_MEAN, S_TMP, c.vol_fluid, s);
+    k_rhs<<<c.W0.nb, TPB, 0, s>>>(c.L0(), c.W0, c.pin, c.t.p, c.sc.p, S_TMP, b);
+    if (c.nrows) k_rhs_ghost<<<sparse_blocks(c.nrows), TPB, 0, s>>>(c.sp, c.rdlb.p, gval, b);
+    IBM_LAUNCH_CHECK();
+}
+
+// solve A x = b (assembled, in c.b, split) into c.x; returns status
+int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
+{
+    const poisson_opts &o = c.opts;
+    int rc = IBM_ENOCONV, its = 0, outer = 0;
+    double rel = 1.0;
+    if (!c.mixed) {
+        its = bicgstab<double>(c, c.b.p, c.x.p, c.r.p, c.rh.p, c.p.p, c.v.p, c.ph.p, c.sh.p, c.t.p, o.tol, o.max_iter,
+                               true, &c.g64, s, &rc, &rel);
+        if (log_enabled()) fprintf(stderr, "[ibm] fp64: %d iterations to %.3e (rc %d)\n", its, rel, rc);
+    } else {
+        // FP64 iterative refinement around FP32 inner solves
+        const Walk &W = c.W0;
+        k_fill<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, 0.0);
+        k_dot2<double><<<W.nb, TPB, 0, s>>>(W, c.b.p, c.b.p, c.part.p, PSTRIDE);
+        k_fin<<<1, 1024, 0, s>>>(c.part.p, PSTRIDE, W.nb, FIN_SUM, S_TMP2, 0.0, c.sc.p);
+        IBM_LAUNCH_CHECK();
+        read_scalars(c, s);
+        const double bn2 = c.hsc[S_TMP2];
+        for (outer = 0; outer <= o.max_outer; ++outer) {
+            if (bn2 == 0.0) { rc = IBM_OK; rel = 0.0; break; }
+            // r64 = b - A x (pinned) and its norm
+            int np = launch_apply<double>(c, M_PINNED, true, 2, c.x.p, c.r.p, c.b.p, nullptr, c.b.p, nullptr, s);
+            k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
+            IBM_LAUNCH_CHECK();
+            read_scalars(c, s);
+            rel = std::sqrt(c.hsc[S_TMP] / bn2);
+            if (!std::isfinite(rel)) { rc = IBM_EBREAKDOWN; break; }
+            if (rel <= o.tol) { rc = IBM_OK; break; }
+            if (outer == o.max_outer) { rc = IBM_ENOCONV; break; }
+            // inner FP32 solve of A d = r64 (the inner residual vector starts as r64);
+            // it asks only for the reduction still needed, never less than inner_tol
+            k_copy<double, float><<<W.nb, TPB, 0, s>>>(W, c.r.p, c.fr.p);
+            IBM_LAUNCH_CHECK();
+            int irc;
+            double irel;
+            const double itol = std::max(o.inner_tol, 0.5 * o.tol / rel);
+            const int n_in = bicgstab<float>(c, c.fr.p, c.fd.p, c.fr.p, c.frh.p, c.fp.p, c.fv.p, c.fph.p, c.fsh.p,
+                                             c.ft.p, itol, o.max_iter, false, &c.g32, s, &irc, &irel);
+            its += n_in;
+            if (log_enabled())
+                fprintf(stderr, "[ibm] outer %d: rel %.3e, inner tol %.1e: %d iterations to %.2e (rc %d)\n", outer, rel,
+                        itol, n_in, irel, irc);
+            if (irc == IBM_EBREAKDOWN) { rc = irc; break; }
+            k_add<float><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.fd.p);
+            IBM_LAUNCH_CHECK();
+        }
+    }
+    if (stats) {
+        stats->iterations = its;
+        stats->outer_steps = outer;
+        stats->rel_residual = rel;
+        stats->status = rc;
+        stats->levels = (int)c.lv.size();
+        stats->n_fallback = c.n_fallback;
+    }
+    return rc;
+}
+
+}  // namespace
+}  // namespace ibm
+
+// ------------------------------------------------------------------ C ABI
+extern "C" void poisson_default_opts(poisson_opts *o)
+{
+    if (!o) return;
+    o->precision = IBM_PREC_FP64;
+    o->tol = 1e-10;
+    o->max_iter = 200;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->coarse_sweeps = 32;
+    o->inner_tol = 1e-4;
+    o->max_outer = 10;
+    o->use_graph = 1;
+}
+
+extern "C" int32_t poisson_workspace_estimate(int32_t nx, int32_t ny, int32_t nz, int64_t n_rows, int32_t precision,
+                                              size_t *bytes)
+{
+    return guarded([&] {
+        IBM_REQUIRE(bytes && nx > 0 && ny > 0 && nz > 0, IBM_EINVAL, "bad arguments");
+        *bytes = estimate_bytes(nx, ny, nz, n_rows, precision);
+    });
+}
+
+extern "C" int32_t poisson_setup(const ibm_grid *grid, const uint8_t *flags_dev, const ibm_stencils *st,
+                                 const poisson_opts *opts, size_t *workspace_bytes, poisson_ctx **out)
+{
+    return guarded([&] {
+        IBM_REQUIRE(out, IBM_EINVAL, "null output");
+        poisson_ctx *c = setup(grid, flags_dev, st, opts);
+        if (workspace_bytes) *workspace_bytes = c->bytes;
+        *out = c;
+    });
+}
+
+extern "C" int32_t poisson_solve(poisson_ctx *c, const double *f_dev, const double *g_dev, double *x_dev,
+                                 poisson_stats *stats, void *stream)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c && f_dev && x_dev, IBM_EINVAL, "null argument");
+        StreamJoin j(*c, (hipStream_t)stream);
+        hipStream_t s = c->cs;
+        IBM_HIP(hipEventRecord(c->e0, s));
+        assemble_rhs(*c, f_dev, g_dev, c->b.p, s);
+        int rc = solve_core(*c, stats, s);
+        // gauge: volume-weighted fluid mean removed from fluid, ghost and membrane-ghost values
+        k_pinres<<<1, 64, 0, s>>>(c->L0(), c->pin, c->x.p, c->sc.p);
+        k_vsum<double, false><<<c->Wc.nb, TPB, 0, s>>>(c->L0(), c->Wc, c->x.p, c->part.p);
+        fin(*c, c->Wc.nb, FIN_MEAN, S_TMP2, c->vol_fluid, s);
+        k_gauge<<<c->W0.nb, TPB, 0, s>>>(c->L0(), c->W0, c->x.p, c->sc.p, S_TMP2, c->t.p);
+        from_split(*c, c->t.p, x_dev, c->nm, s);
+        IBM_HIP(hipEventRecord(c->e1, s));
+        read_scalars(*c, s);
+        if (stats) {
+            float ms = 0.f;
+            IBM_HIP(hipEventElapsedTime(&ms, c->e0, c->e1));
+            stats->solve_ms = ms;
+            stats->pin_residual = c->hsc[S_TMP];
+        }
+        if (rc == IBM_ENOCONV) throw Error(IBM_ENOCONV, "iteration limit reached");
+        if (rc == IBM_EBREAKDOWN) throw Error(IBM_EBREAKDOWN, "BiCGSTAB breakdown or non-finite values");
+    });
+}
+
+extern "C" int32_t poisson_solve_assembled(poisson_ctx *c, const double *b_dev, double *x_dev, poisson_stats *stats,
+                                           void *stream)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c && b_dev && x_dev, IBM_EINVAL, "null argument");
+        StreamJoin j(*c, (hipStream_t)stream);
+        hipStream_t s = c->cs;
+        IBM_HIP(hipEventRecord(c->e0, s));
+        to_split(*c, b_dev, c->b.p, c->nm, s);
+        int rc = solve_core(*c, stats, s);
+        from_split(*c, c->x.p, x_dev, c->nm, s);
+        IBM_HIP(hipEventRecord(c->e1, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        if (stats) {
+            float ms = 0.f;
+            IBM_HIP(hipEventElapsedTime(&ms, c->e0, c->e1));
+            stats->solve_ms = ms;
+        }
+        if (rc != IBM_OK) throw Error(rc, rc == IBM_ENOCONV ? "iteration limit reached" : "breakdown");
+    });
+}
+
+extern "C" int32_t poisson_apply(poisson_ctx *c, const double *x_dev, double *y_dev, void *stream)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c && x_dev && y_dev, IBM_EINVAL, "null argument");
+        StreamJoin j(*c, (hipStream_t)stream);
+        hipStream_t s = c->cs;
+        to_split(*c, x_dev, c->r.p, c->nm, s);
+        launch_apply<double>(*c, M_PINNED, false, 0, c->r.p, c->t.p, nullptr, nullptr, nullptr, nullptr, s);
+        from_split(*c, c->t.p, y_dev, c->nm, s);
+    });
+}
+
+extern "C" int32_t poisson_assemble_rhs(poisson_ctx *c, const double *f_dev, const double *g_dev, double *b_dev,
+                                        void *stream)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c && f_dev && b_dev, IBM_EINVAL, "null argument");
+        StreamJoin j(*c, (hipStream_t)stream);
+        hipStream_t s = c->cs;
+        assemble_rhs(*c, f_dev, g_dev, c->r.p, s);
+        from_split(*c, c->r.p, b_dev, c->nm, s);
+    });
+}
+
+extern "C" int32_t poisson_precond(poisson_ctx *c, const double *b_dev, double *x_dev, void *stream)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c && b_dev && x_dev, IBM_EINVAL, "null argument");
+        IBM_REQUIRE(!c->mixed, IBM_EINVAL, "poisson_precond needs an FP64 context");
+        StreamJoin j(*c, (hipStream_t)stream);
+        hipStream_t s = c->cs;
+        to_split(*c, b_dev, c->r.p, c->nm, s);
+        k_vsum<double, true><<<c->Wc.nb, TPB, 0, s>>>(c->L0(), c->Wc, c->r.p, c->part.p);
+        fin(*c, c->Wc.nb, FIN_SINK, S_SINKP, 0.0, s);
+        vcycle<double>(*c, c->r.p, c->t.p, c->sc.p + S_SINKP, s);
+        // shift: every active unknown minus the pin value, then the pin itself
+        k_shift<double><<<c->W0.nb, TPB, 0, s>>>(c->L0(), c->W0, c->pin, c->t.p);
+        k_shift_pin<<<1, 1, 0, s>>>(c->pin, c->t.p);
+        from_split(*c, c->t.p, x_dev, c->nm, s);
+        IBM_LAUNCH_CHECK();
+    });
+}
+
+extern "C" int32_t poisson_kernel_timing(poisson_ctx *c, int32_t kernel, int32_t reset, double *total_ms,
+                                         int64_t *launches)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c, IBM_EINVAL, "null context");
+        IBM_REQUIRE(kernel >= -1 && kernel <= PK_XR, IBM_EINVAL, "unknown kernel id");
+        if (total_ms) *total_ms = c->prof_ms;
+        if (launches) *launches = c->prof_count;
+        if (reset) { c->prof_ms = 0.0; c->prof_count = 0; c->prof_used = 0; }
+        c->prof_kernel = kernel;
+    });
+}
+
+extern "C" int32_t poisson_level_info(poisson_ctx *c, int32_t *levels, int64_t *n_unknowns, int64_t *n_ghost,
+                                      int64_t *n_mghost)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c, IBM_EINVAL, "null context");
+        if (levels) *levels = (int32_t)c->lv.size();
+        if (n_unknowns) *n_unknowns = c->N + c->nm;
+        if (n_ghost) *n_ghost = c->ng;
+        if (n_mghost) *n_mghost = c->nm;
+    });
+}
+
+extern "C" void poisson_destroy(poisson_ctx *c)
+{
+    if (c) {
+        (void)hipStreamSynchronize(c->cs);
+        delete c;
+    }
+}
