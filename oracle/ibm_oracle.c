@@ -972,6 +972,7 @@ static void fine_smooth(MG *M, double *x, const double *b)
     const Grid *g = &S->g;
     int nx = g->n[0], ny = g->n[1], nz = g->n[2];
     for (int color = 0; color < 2; ++color) {
+        /* regular fluid cells of this colour: their neighbours all have the other colour */
 #pragma omp parallel for
         for (int k = 0; k < nz; ++k)
             for (int j = 0; j < ny; ++j)
@@ -979,11 +980,25 @@ static void fine_smooth(MG *M, double *x, const double *b)
                     if (((i + j + k) & 1) != color) continue;
                     int64_t p = IDX(g->n, i, j, k);
                     uint8_t f = S->flags[p];
-                    if (f & F_SOLID) continue;
+                    if (f & (F_SOLID | F_MGHOST)) continue;
                     double s = cell_scale(g, i, j, k);
                     /* fluid row: sum c (nb - xp) = b  =>  xp = (sum c nb - b) / s */
                     x[p] = (fluid_offsum_elim(S, x, b, i, j, k, p) - b[p]) / s;
                 }
+        /* then the membrane-adjacent cells of this colour, all from the same
+         * iterate (their eliminated ghost stencils may reach each other) */
+#pragma omp parallel for
+        for (int32_t m = 0; m < S->nm; ++m) {
+            int64_t p = S->row_cell[S->ng + m];
+            int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
+            if (((i + j + k) & 1) != color) continue;
+            M->tmp[m] = (fluid_offsum_elim(S, x, b, i, j, k, p) - b[p]) / cell_scale(g, i, j, k);
+        }
+        for (int32_t m = 0; m < S->nm; ++m) {
+            int64_t p = S->row_cell[S->ng + m];
+            int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
+            if (((i + j + k) & 1) == color) x[p] = M->tmp[m];
+        }
         ghost_jacobi(M, x, b);
     }
 }
