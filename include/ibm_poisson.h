@@ -99,7 +99,11 @@ typedef struct poisson_stats {
 } poisson_stats;
 
 /* Defaults: FP64, tol 1e-10, 200 iterations, V(2,2), 32 coarse sweeps,
- * inner_tol 1e-5, max_outer 10, graphs on. */
+ * inner_tol 1e-3, max_outer 10, graphs on.  Each inner solve of the mixed
+ * form asks for max(inner_tol, tol / (2 rel)) where rel is the current FP64
+ * relative residual: tighter inner tolerances buy little, because the BF16
+ * rounding of the coarse right-hand sides makes the preconditioner slightly
+ * non-linear and the inner Krylov iteration slows down below ~1e-3. */
 void poisson_default_opts(poisson_opts *opts);
 
 /*

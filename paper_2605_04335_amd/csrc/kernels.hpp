@@ -44,6 +44,12 @@ __device__ __forceinline__ void st<bf16>(bf16 *a, long long i, double v) { a[i] 
 template <>
 __device__ __forceinline__ double ld<bf16>(const bf16 *a, long long i) { return (double)(float)a[i]; }
 
+// v rounded to the precision of storage type T
+template <class T>
+__device__ __forceinline__ double round_to(double v) { return (double)(T)v; }
+template <>
+__device__ __forceinline__ double round_to<bf16>(double v) { return (double)(float)(bf16)(float)v; }
+
 // division by a runtime-invariant 32-bit divisor (round-up multiplier)
 struct FDiv {
     uint32_t d, m, s;
@@ -119,6 +125,9 @@ inline Geo make_geo(int H, int ny, int nz)
     g.nb = (int)((n + 7) / 8 * 8);
     return g;
 }
+// tiles over cells in natural x order (nx instead of H): the restriction
+inline Geo make_geo_nat(int nx, int ny, int nz) { return make_geo(nx, ny, nz); }
+
 // Tile of this block (XCD-contiguous remap); false for padding blocks.
 __device__ __forceinline__ bool geo_tile(const Geo &G, int &h, int &j, int &k0, int &k1)
 {
@@ -198,9 +207,15 @@ __device__ __forceinline__ void decode_slot(const Lv &L, long long s, int &c, in
 
 __device__ __forceinline__ bool active0(uint8_t f) { return !(f & F_SOLID) || (f & F_GHOST); }
 
+// coarse-level mask bits: active cell, then the six faces that are open
+// (both cells active and no membrane cut between them), each stored in both
+// cells so a row needs only its own byte
+enum : uint8_t { CM_ACT = 1, CM_PX = 2, CM_PY = 4, CM_PZ = 8, CM_MX = 16, CM_MY = 32, CM_MZ = 64 };
+
 // Sum over the open faces of coefficient * neighbour value, and the diagonal.
 // xo is the other colour's array (base of that colour).  FINE: the faces of a
-// regular level-0 cell are open inside the domain; coarse: open-face bits.
+// regular level-0 cell are open inside the domain; coarse: the cell's own
+// open-face bits (fo is not read).
 template <bool FINE, class T>
 __device__ __forceinline__ double nbsum(const Lv &L, const T *xo, const uint8_t *fo, int h, int j, int k, int i,
                                         uint8_t fm, double &dg)
@@ -218,12 +233,12 @@ __device__ __forceinline__ double nbsum(const Lv &L, const T *xo, const uint8_t 
         if (k > 0) { double c = L.cm[2][k]; acc += c * ld(xo, row + h - pl); d += c; }
     } else {
         const long long pl = (long long)L.H * L.ny;
-        if (fm & 2) { double c = L.cp[0][i]; acc += c * ld(xo, row + h + p); d += c; }
-        if (i > 0 && (fo[row + h + p - 1] & 2)) { double c = L.cm[0][i]; acc += c * ld(xo, row + h + p - 1); d += c; }
-        if (fm & 4) { double c = L.cp[1][j]; acc += c * ld(xo, row + h + L.H); d += c; }
-        if (j > 0 && (fo[row + h - L.H] & 4)) { double c = L.cm[1][j]; acc += c * ld(xo, row + h - L.H); d += c; }
-        if (fm & 8) { double c = L.cp[2][k]; acc += c * ld(xo, row + h + pl); d += c; }
-        if (k > 0 && (fo[row + h - pl] & 8)) { double c = L.cm[2][k]; acc += c * ld(xo, row + h - pl); d += c; }
+        if (fm & CM_PX) { double c = L.cp[0][i]; acc += c * ld(xo, row + h + p); d += c; }
+        if (fm & CM_MX) { double c = L.cm[0][i]; acc += c * ld(xo, row + h + p - 1); d += c; }
+        if (fm & CM_PY) { double c = L.cp[1][j]; acc += c * ld(xo, row + h + L.H); d += c; }
+        if (fm & CM_MY) { double c = L.cm[1][j]; acc += c * ld(xo, row + h - L.H); d += c; }
+        if (fm & CM_PZ) { double c = L.cp[2][k]; acc += c * ld(xo, row + h + pl); d += c; }
+        if (fm & CM_MZ) { double c = L.cm[2][k]; acc += c * ld(xo, row + h - pl); d += c; }
     }
     dg = d;
     return acc;
@@ -245,12 +260,12 @@ __device__ __forceinline__ double diag_only(const Lv &L, const uint8_t *fo, int 
         if (k + 1 < L.nz) d += L.cp[2][k];
         if (k > 0) d += L.cm[2][k];
     } else {
-        if (fm & 2) d += L.cp[0][i];
-        if (i > 0 && (fo[row + h + p - 1] & 2)) d += L.cm[0][i];
-        if (fm & 4) d += L.cp[1][j];
-        if (j > 0 && (fo[row + h - L.H] & 4)) d += L.cm[1][j];
-        if (fm & 8) d += L.cp[2][k];
-        if (k > 0 && (fo[row + h - pl] & 8)) d += L.cm[2][k];
+        if (fm & CM_PX) d += L.cp[0][i];
+        if (fm & CM_MX) d += L.cm[0][i];
+        if (fm & CM_PY) d += L.cp[1][j];
+        if (fm & CM_MY) d += L.cm[1][j];
+        if (fm & CM_PZ) d += L.cp[2][k];
+        if (fm & CM_MZ) d += L.cm[2][k];
     }
     return d;
 }
@@ -305,57 +320,6 @@ __device__ __forceinline__ double mrow(const Lv &L, const Sp &S, const T *x, int
 enum { M_PINNED = 0, M_PINZERO = 1, M_UNPINNED = 2 };
 
 // ---------------------------------------------------------------- level-0 operator
-// y = A x on regular cells (RES: y = b - A x, with the sink at the pin);
-// skips membrane cells; solid cells (incl. ghosts, padding) get 0.  Dots of
-// y with u1 / u2 (u2 NULL: with y itself).
-template <class T, int MODE, bool RES, int ND>
-__global__ void __launch_bounds__(TPB) k0_apply(Lv L, Geo G, long long pin, const T *x, T *y, const T *b,
-                                                const double *sink, const T *u1, const T *u2, double *part,
-                                                int pstride)
-{
-    Acc<3> a;
-    a.v[0] = a.v[1] = a.v[2] = 0.0;
-    int h, j, k0, k1;
-    if (geo_tile(G, h, j, k0, k1)) {
-        for (int k = k0; k < k1; ++k)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const long long s = slot(L, c, h, j, k);
-                const uint8_t f = L.f[s];
-                if (f & F_MGHOST) continue;
-                double out;
-                if (f & F_SOLID) {
-                    out = 0.0;
-                } else {
-                    const int i = 2 * h + ((c + j + k) & 1);
-                    const double xp = ld(x, s);
-                    double dg;
-                    double ax = nbsum<true>(L, x + (1 - c) * L.Nh, L.f + (1 - c) * L.Nh, h, j, k, i, f, dg) - dg * xp;
-                    if (s == pin && MODE == M_PINNED) ax = -dg * xp;
-                    if (s == pin && MODE == M_PINZERO) ax = 0.0;
-                    if (RES) {
-                        double bb = ld(b, s);
-                        if (s == pin && sink) bb -= sink[0];
-                        out = bb - ax;
-                    } else {
-                        out = ax;
-                    }
-                }
-                st(y, s, out);
-                const double yo = ld(y, s);
-                if (ND >= 1) a.v[0] += ld(u1, s) * yo;
-                if (ND >= 2) a.v[1] += (u2 ? ld(u2, s) : yo) * yo;
-                if (ND >= 3) a.v[2] += yo * yo;
-            }
-    }
-    if constexpr (ND > 0) {
-        Acc<ND> r;
-#pragma unroll
-        for (int q = 0; q < ND; ++q) r.v[q] = a.v[q];
-        block_reduce<ND>(r, part, pstride, blockIdx.x);
-    }
-}
-
 // ghost rows and membrane rows of the operator (one launch for both)
 template <class T, bool RES, int ND>
 __global__ void __launch_bounds__(TPB) k0_sparse(Lv L, Sp S, const T *x, T *y, const T *b, const T *u1,
@@ -391,53 +355,266 @@ __global__ void __launch_bounds__(TPB) k0_sparse(Lv L, Sp S, const T *x, T *y, c
     }
 }
 
-// ---------------------------------------------------------------- smoother
-// Gauss-Seidel half-sweep of colour c over the regular cells of a level.
-// ZMODE 1: first red sweep from a zero iterate (neighbours are zero, every
-// slot of the colour is written); ZMODE 2: first black sweep (reads the new
-// red values, writes zeros to skipped slots).  bsh: FINE - the sink at the
-// pin slot; coarse - the level mean subtracted from every active RHS.
-template <bool FINE, class T, class TB, int ZMODE>
-__global__ void __launch_bounds__(TPB) k_sweep(Lv L, Geo G, long long pin, T *x, const TB *b, const double *bsh,
-                                               int c, int zero_other = 0)
+// Per-column constants of a level-0 stencil walk in one colour: x
+// coefficients and neighbour offsets for both parities of i (which
+// alternates with k), y coefficients and offsets.  Walls carry a zero
+// coefficient and a clamped (in-bounds) offset, so loads need no branches.
+struct Col0 {
+    double cpx[2], cmx[2], cpy, cmy;
+    int oxp[2], oxm[2];
+    long long oyp, oym;
+};
+__device__ __forceinline__ Col0 col0(const Lv &L, int c, int h, int j)
+{
+    Col0 q;
+    const int pa = (c + j) & 1;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int p = pa ^ t;
+        const int i = 2 * h + p;
+        const bool xp = i + 1 < L.nx, xm = i > 0 && i < L.nx;
+        q.cpx[t] = xp ? L.cp[0][i] : 0.0;
+        q.cmx[t] = xm ? L.cm[0][i] : 0.0;
+        q.oxp[t] = xp ? p : 0;
+        q.oxm[t] = xm ? p - 1 : 0;
+    }
+    q.cpy = j + 1 < L.ny ? L.cp[1][j] : 0.0;
+    q.cmy = j > 0 ? L.cm[1][j] : 0.0;
+    q.oyp = j + 1 < L.ny ? (long long)L.H : 0;
+    q.oym = j > 0 ? -(long long)L.H : 0;
+    return q;
+}
+
+// sum of coefficient * other-colour neighbour at slot s of plane k, and the diagonal
+template <class T>
+__device__ __forceinline__ double col0_sum(const Lv &L, const Col0 &q, const T *__restrict__ xo, long long s, int k,
+                                           long long pl, double &dg)
+{
+    // parity of i alternates with k: select (constant indices keep q in registers)
+    const bool t = k & 1;
+    const double cpx = t ? q.cpx[1] : q.cpx[0], cmx = t ? q.cmx[1] : q.cmx[0];
+    const int oxp = t ? q.oxp[1] : q.oxp[0], oxm = t ? q.oxm[1] : q.oxm[0];
+    const double czp = L.cp[2][k], czm = L.cm[2][k];  // zero at the walls
+    const long long ozp = k + 1 < L.nz ? pl : 0, ozm = k > 0 ? -pl : 0;
+    dg = cpx + cmx + q.cpy + q.cmy + czp + czm;
+    return cpx * ld(xo, s + oxp) + cmx * ld(xo, s + oxm) + q.cpy * ld(xo, s + q.oyp) + q.cmy * ld(xo, s + q.oym) +
+           czp * ld(xo, s + ozp) + czm * ld(xo, s + ozm);
+}
+
+// Coarse-level Gauss-Seidel half-sweep of colour c over the active cells,
+// with the level mean mu subtracted from every RHS.  Faces are taken from the
+// cell's own mask byte: a closed face gets a zero coefficient and reads an
+// in-range slot, so every load of a plane is issued before any arithmetic.
+// ZMODE 1: first red sweep from a zero iterate (diagonal only; every slot of
+// the colour is written); ZMODE 2: first black sweep (skipped slots get 0).
+__device__ __forceinline__ double cmask_sum_dg(const Lv &L, const Col0 &q, uint8_t f, int k, double &cpx,
+                                               double &cmx, double &cpy, double &cmy, double &czp, double &czm)
+{
+    const bool t = k & 1;
+    cpx = (f & CM_PX) ? (t ? q.cpx[1] : q.cpx[0]) : 0.0;
+    cmx = (f & CM_MX) ? (t ? q.cmx[1] : q.cmx[0]) : 0.0;
+    cpy = (f & CM_PY) ? q.cpy : 0.0;
+    cmy = (f & CM_MY) ? q.cmy : 0.0;
+    czp = (f & CM_PZ) ? L.cp[2][k] : 0.0;
+    czm = (f & CM_MZ) ? L.cm[2][k] : 0.0;
+    return cpx + cmx + cpy + cmy + czp + czm;
+}
+
+constexpr int UC = 2;
+template <class T, class TB, int ZMODE>
+__global__ void __launch_bounds__(TPB) k_csweep(Lv L, Geo G, T *__restrict__ x, const TB *__restrict__ b,
+                                                const double *__restrict__ bsh, int c)
 {
     int h, j, k0, k1;
     if (!geo_tile(G, h, j, k0, k1)) return;
-    const double mu = (!FINE && bsh) ? bsh[0] : 0.0;
+    const double mu = bsh ? bsh[0] : 0.0;
     T *xc = x + (long long)c * L.Nh;
     const T *xo = x + (long long)(1 - c) * L.Nh;
-    const uint8_t *fc = L.f + (long long)c * L.Nh, *fo = L.f + (long long)(1 - c) * L.Nh;
+    const uint8_t *fc = L.f + (long long)c * L.Nh;
     const TB *bc = b + (long long)c * L.Nh;
+    const Col0 q = col0(L, c, h, j);
+    const long long pl = (long long)L.H * L.ny;
+    const long long col = h + (long long)L.H * j;
+    for (int kb = k0; kb < k1; kb += UC) {
+        double nb[UC], bb[UC], dg[UC];
+        uint8_t fl[UC];
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+            const int k = min(kb + u, k1 - 1);
+            const long long s = col + pl * k;
+            fl[u] = fc[s];
+            bb[u] = ld(bc, s);
+            double cpx, cmx, cpy, cmy, czp, czm;
+            dg[u] = cmask_sum_dg(L, q, fl[u], k, cpx, cmx, cpy, cmy, czp, czm);
+            if (ZMODE == 1) {
+                nb[u] = 0.0;
+            } else {
+                const bool t = k & 1;
+                const int oxp = t ? q.oxp[1] : q.oxp[0], oxm = t ? q.oxm[1] : q.oxm[0];
+                const long long ozp = k + 1 < L.nz ? pl : 0, ozm = k > 0 ? -pl : 0;
+                nb[u] = cpx * ld(xo, s + oxp) + cmx * ld(xo, s + oxm) + cpy * ld(xo, s + q.oyp) +
+                        cmy * ld(xo, s + q.oym) + czp * ld(xo, s + ozp) + czm * ld(xo, s + ozm);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+            const int k = kb + u;
+            if (k >= k1) continue;
+            const long long s = col + pl * k;
+            const int i = 2 * h + ((c + j + k) & 1);
+            if (!(fl[u] & CM_ACT) || i >= L.nx) {
+                if (ZMODE) st(xc, s, 0.0);
+                continue;
+            }
+            st(xc, s, dg[u] > 0.0 ? (nb[u] - (bb[u] - mu)) / dg[u] : 0.0);
+        }
+    }
+}
+
+// Level-0 Gauss-Seidel half-sweep of colour c (ordinary mode): xc, bc, fc
+// are this colour's arrays, xo the other colour's.  Four planes per step,
+// all loads issued before any store.  pin_s: the pin's slot within this
+// colour (or -1), whose RHS carries the sink.
+constexpr int U0 = 4;
+template <class T>
+__global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T *__restrict__ xc,
+                                                const T *__restrict__ xo, const T *__restrict__ bc,
+                                                const uint8_t *__restrict__ fc, const double *__restrict__ sink, int c)
+{
+    int h, j, k0, k1;
+    if (!geo_tile(G, h, j, k0, k1)) return;
+    const Col0 q = col0(L, c, h, j);
+    const long long pl = (long long)L.H * L.ny;
+    const long long col = h + (long long)L.H * j;
+    for (int kb = k0; kb < k1; kb += U0) {
+        double nb[U0], bb[U0], dg[U0];
+        uint8_t fl[U0];
+#pragma unroll
+        for (int u = 0; u < U0; ++u) {
+            const int k = min(kb + u, k1 - 1);
+            const long long s = col + pl * k;
+            fl[u] = fc[s];
+            bb[u] = ld(bc, s);
+            nb[u] = col0_sum(L, q, xo, s, k, pl, dg[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U0; ++u) {
+            const long long s = col + pl * (kb + u);
+            if (kb + u >= k1 || (fl[u] & (F_SOLID | F_MGHOST))) continue;
+            double b0 = bb[u];
+            if (s == pin_s) b0 -= sink[0];
+            st(xc, s, (nb[u] - b0) / dg[u]);
+        }
+    }
+}
+
+// First level-0 half-sweep of a V-cycle, from a zero iterate: every regular
+// cell of colour c gets -b/diag (its neighbours are zero), every other slot
+// of both colours gets 0.
+template <class T>
+__global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_s, T *__restrict__ xc,
+                                                     T *__restrict__ xo, const T *__restrict__ bc,
+                                                     const uint8_t *__restrict__ fc, const double *__restrict__ sink,
+                                                     int c)
+{
+    int h, j, k0, k1;
+    if (!geo_tile(G, h, j, k0, k1)) return;
+    const Col0 q = col0(L, c, h, j);
+    const long long pl = (long long)L.H * L.ny;
+    const long long col = h + (long long)L.H * j;
     for (int k = k0; k < k1; ++k) {
-        const long long s = h + (long long)L.H * (j + (long long)L.ny * k);
-        // from zero with membrane rows: the other colour must read as zero
-        // before its own sweep (membrane rows of this colour read it)
-        if (ZMODE == 1 && zero_other) st(x + (long long)(1 - c) * L.Nh, s, 0.0);
+        const long long s = col + pl * k;
+        const bool t = k & 1;
+        const double dg = (t ? q.cpx[1] : q.cpx[0]) + (t ? q.cmx[1] : q.cmx[0]) + q.cpy + q.cmy + L.cp[2][k] + L.cm[2][k];
+        double b0 = ld(bc, s);
+        if (s == pin_s) b0 -= sink[0];
         const uint8_t f = fc[s];
-        const int i = 2 * h + ((c + j + k) & 1);
-        const bool skip = FINE ? (f & (F_SOLID | F_MGHOST)) != 0 : !(f & 1);
-        if (skip || i >= L.nx) {
-            if (ZMODE) st(xc, s, 0.0);
-            continue;
+        st(xc, s, (f & (F_SOLID | F_MGHOST)) ? 0.0 : -b0 / dg);
+        st(xo, s, 0.0);
+    }
+}
+
+// Level-0 operator on the regular cells of both colours: y = A x, or
+// y = b - A x with the sink at the pin (RES); membrane cells are left to the
+// sparse kernel, solid cells get 0.  Dots of y with u1, u2 (u2 NULL: with y
+// itself).  Both colours' loads of a plane are issued together.
+template <class T, int MODE, bool RES>
+__device__ __forceinline__ bool apply_out(uint8_t f, double xv, double nsum, double dg, double bv, long long s,
+                                          long long pin, const double *sink, double &out)
+{
+    if (f & F_MGHOST) return false;
+    if (f & F_SOLID) {
+        out = 0.0;
+        return true;
+    }
+    double axv = nsum - dg * xv;
+    if (s == pin && MODE == M_PINNED) axv = -dg * xv;
+    if (s == pin && MODE == M_PINZERO) axv = 0.0;
+    if (RES) {
+        if (s == pin && sink) bv -= sink[0];
+        out = bv - axv;
+    } else {
+        out = axv;
+    }
+    return true;
+}
+
+template <class T, int MODE, bool RES, int ND>
+__global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, const T *__restrict__ x, T *__restrict__ y,
+                                                 const T *__restrict__ b, const double *__restrict__ sink,
+                                                 const T *__restrict__ u1, const T *__restrict__ u2, double *part,
+                                                 int pstride)
+{
+    double a0 = 0.0, a1 = 0.0;
+    int h, j, k0, k1;
+    if (geo_tile(G, h, j, k0, k1)) {
+        const long long pl = (long long)L.H * L.ny, Nh = L.Nh;
+        const long long col = h + (long long)L.H * j;
+        const Col0 q0 = col0(L, 0, h, j), q1 = col0(L, 1, h, j);
+        for (int k = k0; k < k1; ++k) {
+            const long long s = col + pl * k, t = Nh + s;
+            const uint8_t f0 = L.f[s], f1 = L.f[t];
+            const double x0 = ld(x, s), x1 = ld(x, t);
+            double d0, d1;
+            const double n0 = col0_sum(L, q0, x + Nh, s, k, pl, d0);
+            const double n1 = col0_sum(L, q1, x, s, k, pl, d1);
+            const double b0 = RES ? ld(b, s) : 0.0, b1 = RES ? ld(b, t) : 0.0;
+            const double v0 = ND >= 1 ? ld(u1, s) : 0.0, v1 = ND >= 1 ? ld(u1, t) : 0.0;
+            const double w0 = (ND >= 2 && u2) ? ld(u2, s) : 0.0, w1 = (ND >= 2 && u2) ? ld(u2, t) : 0.0;
+            double o;
+            if (apply_out<T, MODE, RES>(f0, x0, n0, d0, b0, s, pin, sink, o)) {
+                st(y, s, o);
+                const double yo = ld(y, s);
+                if (ND >= 1) a0 += v0 * yo;
+                if (ND >= 2) a1 += (u2 ? w0 : yo) * yo;
+            }
+            if (apply_out<T, MODE, RES>(f1, x1, n1, d1, b1, t, pin, sink, o)) {
+                st(y, t, o);
+                const double yo = ld(y, t);
+                if (ND >= 1) a0 += v1 * yo;
+                if (ND >= 2) a1 += (u2 ? w1 : yo) * yo;
+            }
         }
-        double bb = ld(bc, s) - mu;
-        if (FINE && bsh && s + (long long)c * L.Nh == pin) bb -= bsh[0];
-        double dg, off;
-        if (ZMODE == 1) {
-            off = 0.0;
-            dg = diag_only<FINE>(L, fo, h, j, k, i, f);
-        } else {
-            off = nbsum<FINE>(L, xo, fo, h, j, k, i, f, dg);
-        }
-        st(xc, s, dg > 0.0 ? (off - bb) / dg : 0.0);
+    }
+    if constexpr (ND == 1) {
+        Acc<1> r;
+        r.v[0] = a0;
+        block_reduce<1>(r, part, pstride, blockIdx.x);
+    } else if constexpr (ND == 2) {
+        Acc<2> r;
+        r.v[0] = a0;
+        r.v[1] = a1;
+        block_reduce<2>(r, part, pstride, blockIdx.x);
     }
 }
 
 // membrane-adjacent cells of one colour (after the dense half-sweep): across
 // a cut link the neighbour's ghost unknown is eliminated, i.e. replaced by
 // the current value of its stencil, sum w x - b/sG
+// All cells of the colour read the same iterate (their eliminated stencils
+// may reach each other): new values go to tmp, k0_mscat writes them.
 template <class T>
-__global__ void __launch_bounds__(TPB) k0_msweep(Lv L, Sp S, T *x, const T *b, int color)
+__global__ void __launch_bounds__(TPB) k0_msweep(Lv L, Sp S, const T *x, const T *b, int color, double *tmp)
 {
     for (int m = blockIdx.x * TPB + threadIdx.x; m < S.nm; m += gridDim.x * TPB) {
         if (S.mcolor[m] != color) continue;
@@ -461,8 +638,15 @@ __global__ void __launch_bounds__(TPB) k0_msweep(Lv L, Sp S, T *x, const T *b, i
             off += cf[q] * v;
             s += cf[q];
         }
-        st(x, u, (off - ld(b, u)) / s);
+        tmp[m] = (off - ld(b, u)) / s;
     }
+}
+
+template <class T>
+__global__ void __launch_bounds__(TPB) k0_mscat(Sp S, T *x, int color, const double *tmp)
+{
+    for (int m = blockIdx.x * TPB + threadIdx.x; m < S.nm; m += gridDim.x * TPB)
+        if (S.mcolor[m] == color) st(x, S.mslot[m], tmp[m]);
 }
 
 // Jacobi on every ghost unknown, staged so that all rows read the same iterate
@@ -552,16 +736,123 @@ __device__ __forceinline__ double restrict_one(const Lv &F, const Lv &C, long lo
     return (C.f[sc] & 1) ? C.w[0][I] * C.w[1][J] * C.w[2][K] * ld(bc, sc) : 0.0;
 }
 
+// one thread per coarse cell in natural x order (Gc tiles I over C.nx), so a
+// wave reads the children's rows with unit stride
 template <bool FINE, class T, class TB, class TBc>
 __global__ void __launch_bounds__(TPB) k_restrict(Lv F, Lv C, Geo Gc, long long pin, const T *x, const TB *b,
                                                   const double *bsh, const T *rsp, TBc *bc, double *part)
 {
     Acc<1> a;
     a.v[0] = 0.0;
-    int h, j, k0, k1;
-    if (geo_tile(Gc, h, j, k0, k1))
-        for (int k = k0; k < k1; ++k)
-            for (int c = 0; c < 2; ++c) a.v[0] += restrict_one<FINE>(F, C, pin, x, b, bsh, rsp, bc, c, h, j, k);
+    int I, J, k0, k1;
+    if (geo_tile(Gc, I, J, k0, k1))
+        for (int K = k0; K < k1; ++K) {
+            const int cc = (I + J + K) & 1;
+            a.v[0] += restrict_one<FINE>(F, C, pin, x, b, bsh, rsp, bc, cc, I >> 1, J, K);
+        }
+    block_reduce<1>(a, part, 0, blockIdx.x);
+}
+
+// Level-0 residual of the unpinned system (sink at the pin) fused with its
+// restriction into level 1: one thread per coarse (I, J) column walks its K
+// range; the 8 children of coarse cell (I, J, K) are half-index I of both
+// colours in rows 2J, 2J+1 and planes 2K, 2K+1.  The other-colour values of
+// planes 2K-1 .. 2K+2 of the two rows stay in registers (two new planes per
+// step).  Children that carry a ghost or membrane row take their residual
+// from rsp (written by k0_sparse_res).  Coarse RHS = volume-weighted mean
+// over the active children; partial sums of V_C b_C for the coarse mean.
+template <class T, class TBc>
+__global__ void __launch_bounds__(TPB) k0_restrict_res(Lv F, Lv C, Geo Gc, long long pin, const T *__restrict__ x,
+                                                       const T *__restrict__ b, const double *__restrict__ sink,
+                                                       const T *__restrict__ rsp, TBc *__restrict__ bc, double *part)
+{
+    Acc<1> a;
+    a.v[0] = 0.0;
+    int I, J, k0, k1;
+    if (geo_tile(Gc, I, J, k0, k1)) {
+        const long long Nh = F.Nh, H = F.H, pl = H * F.ny;
+        const double snk = sink ? sink[0] : 0.0;
+        // x: coefficients of the two cells i = 2I + dx; the outer neighbour of
+        // i = 2I is half I-1, of i = 2I+1 half I+1 (clamped, zero coefficient)
+        double cpx[2], cmx[2], wx[2];
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            const int i = 2 * I + dx;
+            cpx[dx] = i + 1 < F.nx ? F.cp[0][i] : 0.0;
+            cmx[dx] = i > 0 ? F.cm[0][i] : 0.0;
+            wx[dx] = F.w[0][i];
+        }
+        const int hm = I > 0 ? I - 1 : I, hp = 2 * I + 2 < F.nx ? I + 1 : I;
+        double cpy[2], cmy[2], wy[2];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const int j = 2 * J + dy;
+            cpy[dy] = j + 1 < F.ny ? F.cp[1][j] : 0.0;
+            cmy[dy] = j > 0 ? F.cm[1][j] : 0.0;
+            wy[dy] = F.w[1][j];
+        }
+        const long long rowm = H * max(2 * J - 1, 0), row0 = H * (2 * J), row1 = H * (2 * J + 1),
+                        rowp = H * min(2 * J + 2, F.ny - 1);
+        // v[c][dy][q]: colour c, row 2J+dy, plane 2K-1+q
+        double v[2][2][4];
+        auto ldcol = [&](int kk, int q) {
+            const long long z = pl * min(max(kk, 0), F.nz - 1);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                v[c][0][q] = ld(x, c * Nh + I + row0 + z);
+                v[c][1][q] = ld(x, c * Nh + I + row1 + z);
+            }
+        };
+        ldcol(2 * k0 - 1, 0);
+        ldcol(2 * k0, 1);
+        for (int K = k0; K < k1; ++K) {
+            ldcol(2 * K + 1, 2);
+            ldcol(2 * K + 2, 3);
+            double sv = 0.0, svr = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+                const int c = (dx + dy + dz) & 1, o = 1 - c;
+                const int k = 2 * K + dz;
+                const long long zk = pl * k;
+                const long long s = c * Nh + I + (dy ? row1 : row0) + zk;
+                const uint8_t f = F.f[s];
+                if (!active0(f)) continue;
+                double r;
+                if (f & (F_GHOST | F_MGHOST)) {
+                    r = ld(rsp, s);
+                } else {
+                    const double xv = v[c][dy][1 + dz];
+                    const double xin = v[o][dy][1 + dz];
+                    const double xout = ld(x, o * Nh + (dx ? hp : hm) + (dy ? row1 : row0) + zk);
+                    const double xpx = dx ? xout : xin, xmx = dx ? xin : xout;
+                    const double xpy = dy ? ld(x, o * Nh + I + rowp + zk) : v[o][1][1 + dz];
+                    const double xmy = dy ? v[o][0][1 + dz] : ld(x, o * Nh + I + rowm + zk);
+                    const double xpz = v[o][dy][2 + dz], xmz = v[o][dy][dz];
+                    const double czp = F.cp[2][k], czm = F.cm[2][k];  // zero at the walls
+                    const double dg = cpx[dx] + cmx[dx] + cpy[dy] + cmy[dy] + czp + czm;
+                    const double n = cpx[dx] * xpx + cmx[dx] * xmx + cpy[dy] * xpy + cmy[dy] * xmy + czp * xpz +
+                                     czm * xmz;
+                    double bv = ld(b, s);
+                    if (s == pin) bv -= snk;
+                    r = bv - (n - dg * xv);
+                }
+                const double V = wx[dx] * wy[dy] * F.w[2][k];
+                sv += V;
+                svr += V * r;
+            }
+            const long long sc = slot(C, (I + J + K) & 1, I >> 1, J, K);
+            st(bc, sc, sv > 0.0 ? svr / sv : 0.0);
+            if (C.f[sc] & 1) a.v[0] += C.w[0][I] * C.w[1][J] * C.w[2][K] * ld(bc, sc);
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    v[c][d][0] = v[c][d][2];
+                    v[c][d][1] = v[c][d][3];
+                }
+        }
+    }
     block_reduce<1>(a, part, 0, blockIdx.x);
 }
 
@@ -601,30 +892,111 @@ __device__ __forceinline__ void prolong_one(const Lv &F, const Lv &C, const PMap
     st(xf, s, ld(xf, s) + interp(C, M, xc, i, j, k));
 }
 
-template <bool FINE, class Tc, class Tf>
-__global__ void __launch_bounds__(TPB) k_prolong(Lv F, Lv C, PMap M, Geo G, const Tc *xc, Tf *xf)
+// Prolongation by coarse column: one thread per coarse (I, J) column walks
+// its K range with the 3x3 coarse neighbourhoods of planes K-1, K, K+1 in
+// registers (one new plane per step) and corrects the 8 children of each
+// coarse cell: trilinear in physical coordinates, clamped at the walls, in
+// the precision of the fine iterate.
+// SKIP_RED: the red half-sweep that follows overwrites every regular red
+// cell without reading it, so only black slots (and, on level 0, the red
+// ghost and membrane cells, which later rows read) receive the correction.
+template <bool FINE, class Tc, class Tf, bool SKIP_RED>
+__global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, const Tc *__restrict__ xc,
+                                                   Tf *__restrict__ xf)
 {
-    int h, j, k0, k1;
-    if (!geo_tile(G, h, j, k0, k1)) return;
-    for (int k = k0; k < k1; ++k)
-        for (int c = 0; c < 2; ++c) prolong_one<FINE>(F, C, M, xc, xf, c, h, j, k);
+    typedef Tf R;
+    int I, J, k0, k1;
+    if (!geo_tile(Gc, I, J, k0, k1)) return;
+    const int Ie[3] = {max(I - 1, 0), I, min(I + 1, C.nx - 1)};
+    const int Jb[3] = {max(J - 1, 0), J, min(J + 1, C.ny - 1)};
+    R va[3][3], vb[3][3], vn[3][3];
+    auto plane = [&](int kk, R (&v)[3][3]) {
+        const long long zo = (long long)C.H * C.ny * kk;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const long long sc = (((Ie[e] + Jb[b] + kk) & 1) ? C.Nh : 0) + (Ie[e] >> 1) +
+                                     (long long)C.H * Jb[b] + zo;
+                v[b][e] = (R)ld(xc, sc);
+            }
+    };
+    // per child direction: does the 2-point box start at the cell (offset 1)
+    // or at its lower neighbour (offset 0), and the weight of the upper point
+    bool ex[2], ey[2];
+    R tx[2], ty[2];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        ex[d] = M.pi[0][2 * I + d] != I - 1;
+        tx[d] = (R)M.pt[0][2 * I + d];
+        ey[d] = M.pi[1][2 * J + d] != J - 1;
+        ty[d] = (R)M.pt[1][2 * J + d];
+    }
+    const long long fpl = (long long)F.H * F.ny;
+    plane(max(k0 - 1, 0), va);
+    plane(k0, vb);
+    for (int K = k0; K < k1; ++K) {
+        plane(min(K + 1, C.nz - 1), vn);
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz) {
+            const int k = 2 * K + dz;
+            const bool ez = M.pi[2][k] != K - 1;
+            const R tz = (R)M.pt[2][k];
+            // z, then y, then x
+            R zz[3][3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    zz[b][e] = ez ? (1 - tz) * vb[b][e] + tz * vn[b][e] : (1 - tz) * va[b][e] + tz * vb[b][e];
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                R yy[3];
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    yy[e] = ey[dy] ? (1 - ty[dy]) * zz[1][e] + ty[dy] * zz[2][e]
+                                   : (1 - ty[dy]) * zz[0][e] + ty[dy] * zz[1][e];
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx) {
+                    const int cf = (dx + dy + dz) & 1;
+                    const long long s = (long long)cf * F.Nh + I + (long long)F.H * (2 * J + dy) + fpl * k;
+                    const uint8_t f = F.f[s];
+                    if (FINE ? !active0(f) : !(f & 1)) continue;
+                    if (SKIP_RED && cf == 0 && (!FINE || !(f & (F_GHOST | F_MGHOST)))) continue;
+                    const R val = ex[dx] ? (1 - tx[dx]) * yy[1] + tx[dx] * yy[2] : (1 - tx[dx]) * yy[0] + tx[dx] * yy[1];
+                    st(xf, s, ld(xf, s) + val);
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                va[b][e] = vb[b][e];
+                vb[b][e] = vn[b][e];
+            }
+    }
 }
 
 // ---------------------------------------------------------------- coarse tail in one workgroup
-// The smallest levels (each <= TAIL_MAX cells) run as one 1024-thread block:
-// same operations as the grid kernels, separated by block barriers; the
-// coarse means are block reductions.
-constexpr int TAIL_MAX = 32768;
+// The smallest levels run as one 1024-thread block with their masks, iterates
+// and right-hand sides staged in LDS: the same operations as the grid
+// kernels, separated by block barriers; the coarse means are block
+// reductions.  Only the first tail level's RHS comes from global memory and
+// only its iterate goes back.
 constexpr int TAIL_T = 1024;
+constexpr int TAIL_LDS = 60 * 1024;  // bytes of dynamic LDS the tail may use
 
 struct TailLevel {
-    Lv L;
-    PMap M;          // prolongation onto this level from the next one
+    Lv L;             // global views (coefficients, maps); L.f is replaced by the LDS mask
+    PMap M;           // prolongation onto this level from the next one
     double volA;
-    void *x, *b, *r; // typed by the caller
+    void *xg;         // global iterate of the first tail level
+    const void *bg;   // global RHS of the first tail level
+    int moff, xoff, boff;  // LDS byte offsets
 };
 struct Tail {
-    int n;           // levels in the tail (>= 1)
+    int n;            // levels in the tail (>= 1)
     TailLevel t[8];
     int nu1, nu2, ncs;
 };
@@ -644,8 +1016,8 @@ __device__ double tail_sum(double v)
     return s;
 }
 
-template <class Tc, class TB>
-__device__ void tail_sweep(const Lv &L, Tc *x, const TB *b, double mu, int c, bool zero)
+template <class Tc>
+__device__ void tail_sweep(const Lv &L, Tc *x, const Tc *b, double mu, int c, bool zero)
 {
     const long long n = (long long)L.H * L.ny * L.nz;
     for (long long q = threadIdx.x; q < n; q += blockDim.x) {
@@ -671,30 +1043,49 @@ __device__ void tail_sweep(const Lv &L, Tc *x, const TB *b, double mu, int c, bo
     __syncthreads();
 }
 
+// view of tail level l whose mask lives in LDS
+__device__ __forceinline__ Lv tail_lv(const Tail &T, int l, unsigned char *smem)
+{
+    Lv L = T.t[l].L;
+    L.f = (const uint8_t *)(smem + T.t[l].moff);
+    return L;
+}
+
 template <class Tc, class TB>
 __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
 {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double mus[8];
-    // level t[0]'s RHS was restricted by the caller; its mean is mean0
+    for (int l = 0; l < T.n; ++l) {
+        uint8_t *m = (uint8_t *)(smem + T.t[l].moff);
+        const long long n2 = 2 * T.t[l].L.Nh;
+        for (long long q = threadIdx.x; q < n2; q += blockDim.x) m[q] = T.t[l].L.f[q];
+    }
+    {
+        Tc *b0 = (Tc *)(smem + T.t[0].boff);
+        const TB *bg = (const TB *)T.t[0].bg;
+        const long long n2 = 2 * T.t[0].L.Nh;
+        for (long long q = threadIdx.x; q < n2; q += blockDim.x) b0[q] = (Tc)ld(bg, q);
+    }
     if (threadIdx.x == 0) mus[0] = mean0[0];
     __syncthreads();
     for (int l = 0; l < T.n; ++l) {
-        const Lv &L = T.t[l].L;
-        Tc *x = (Tc *)T.t[l].x;
-        const TB *b = (const TB *)T.t[l].b;
+        const Lv L = tail_lv(T, l, smem);
+        Tc *x = (Tc *)(smem + T.t[l].xoff);
+        const Tc *b = (const Tc *)(smem + T.t[l].boff);
         const double mu = mus[l];
         const bool last = l == T.n - 1;
         const int steps = last ? T.ncs : T.nu1;
         for (int it = 0; it < steps; ++it) {
-            tail_sweep<Tc, TB>(L, x, b, mu, 0, it == 0);
-            tail_sweep<Tc, TB>(L, x, b, mu, 1, it == 0);
+            tail_sweep<Tc>(L, x, b, mu, 0, it == 0);
+            tail_sweep<Tc>(L, x, b, mu, 1, it == 0);
         }
         if (last) break;
-        // restriction to the next level with the block-reduced coarse mean
-        const Lv &C = T.t[l + 1].L;
-        TB *bc = (TB *)T.t[l + 1].b;
+        // residual + restriction into the next level (rounded to the coarse
+        // storage precision), then its volume-weighted mean
+        const Lv C = tail_lv(T, l + 1, smem);
+        Tc *bc = (Tc *)(smem + T.t[l + 1].boff);
         const long long nc = (long long)C.H * C.ny * C.nz;
-        double part = 0.0;
         for (long long q = threadIdx.x; q < 2 * nc; q += blockDim.x) {
             const int cc = q >= nc ? 1 : 0;
             const long long qq = q - cc * nc;
@@ -702,16 +1093,30 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
             const long long row = qq / C.H;
             const int J = (int)(row % C.ny), K = (int)(row / C.ny);
             double mub = mu;
-            part += restrict_one<false, Tc, TB, TB>(L, C, -1, x, b, &mub, (const Tc *)nullptr, bc, cc, hc, J, K);
+            restrict_one<false, Tc, Tc, Tc>(L, C, -1, x, b, &mub, (const Tc *)nullptr, bc, cc, hc, J, K);
+            const long long sc = (long long)cc * C.Nh + qq;
+            st(bc, sc, round_to<TB>(ld(bc, sc)));  // coarse storage precision
+        }
+        __syncthreads();
+        double part = 0.0;
+        for (long long q = threadIdx.x; q < 2 * nc; q += blockDim.x) {
+            if (!(C.f[q] & 1)) continue;
+            const int cc = q >= nc ? 1 : 0;
+            const long long qq = q - cc * nc;
+            const int hc = (int)(qq % C.H);
+            const long long row = qq / C.H;
+            const int J = (int)(row % C.ny), K = (int)(row / C.ny);
+            const int I = 2 * hc + ((cc + J + K) & 1);
+            part += C.w[0][I] * C.w[1][J] * C.w[2][K] * ld(bc, q);
         }
         const double tot = tail_sum(part);
         if (threadIdx.x == 0) mus[l + 1] = T.t[l + 1].volA > 0.0 ? tot / T.t[l + 1].volA : 0.0;
         __syncthreads();
     }
     for (int l = T.n - 2; l >= 0; --l) {
-        const Lv &L = T.t[l].L, &C = T.t[l + 1].L;
-        Tc *x = (Tc *)T.t[l].x;
-        const Tc *xc = (const Tc *)T.t[l + 1].x;
+        const Lv L = tail_lv(T, l, smem), C = tail_lv(T, l + 1, smem);
+        Tc *x = (Tc *)(smem + T.t[l].xoff);
+        const Tc *xc = (const Tc *)(smem + T.t[l + 1].xoff);
         const long long n = (long long)L.H * L.ny * L.nz;
         for (long long q = threadIdx.x; q < 2 * n; q += blockDim.x) {
             const int c = q >= n ? 1 : 0;
@@ -721,11 +1126,17 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
             prolong_one<false>(L, C, T.t[l].M, xc, x, c, h, (int)(row % L.ny), (int)(row / L.ny));
         }
         __syncthreads();
-        const TB *b = (const TB *)T.t[l].b;
+        const Tc *b = (const Tc *)(smem + T.t[l].boff);
         for (int it = 0; it < T.nu2; ++it) {
-            tail_sweep<Tc, TB>(L, x, b, mus[l], 0, false);
-            tail_sweep<Tc, TB>(L, x, b, mus[l], 1, false);
+            tail_sweep<Tc>(L, x, b, mus[l], 0, false);
+            tail_sweep<Tc>(L, x, b, mus[l], 1, false);
         }
+    }
+    {
+        const Tc *x0 = (const Tc *)(smem + T.t[0].xoff);
+        Tc *xg = (Tc *)T.t[0].xg;
+        const long long n2 = 2 * T.t[0].L.Nh;
+        for (long long q = threadIdx.x; q < n2; q += blockDim.x) xg[q] = x0[q];
     }
 }
 

@@ -37,11 +37,12 @@ struct Level {
     int H = 0;
     long long N = 0, Nh = 0;
     DBuf<double> cp[3], cm[3], w[3];
-    DBuf<uint8_t> m;                 // split layout: coarse mask (bit0 active, bits1-3 open); level 0 flags
+    DBuf<uint8_t> m;                 // split layout: coarse mask (CM_* bits); level 0 flags
     DBuf<int> pi[3];                 // prolongation map from the coarse parent
     DBuf<double> pt[3];
     double volA = 0.0;               // volume of the active cells
-    Geo geo;
+    Geo geo;                         // tiles over (h, j, k) of one colour
+    Geo geon;                        // tiles over (i, j, k): restriction into this level
     Walk walk;                       // over 2 Nh slots
     DBuf<double> x64, b64;
     DBuf<float> x32;
@@ -75,7 +76,20 @@ void level_geometry(Level &L, const std::vector<double> *f, hipStream_t s)
     L.H = (L.n[0] + 1) / 2;
     L.Nh = (long long)L.H * L.n[1] * L.n[2];
     L.geo = make_geo(L.H, L.n[1], L.n[2]);
+    L.geon = make_geo_nat(L.n[0], L.n[1], L.n[2]);
     L.walk = make_walk(2 * L.Nh);
+}
+
+// LDS layout of one tail level (mask, iterate, RHS), 16-byte aligned pieces
+inline void tail_layout(long long Nh, size_t tsz, int &off, int &moff, int &xoff, int &boff)
+{
+    auto al = [](long long v) { return (int)((v + 15) / 16 * 16); };
+    moff = off;
+    off = al(off + 2 * Nh);
+    xoff = off;
+    off = al(off + 2 * Nh * (long long)tsz);
+    boff = off;
+    off = al(off + 2 * Nh * (long long)tsz);
 }
 
 // slot of natural cell (i,j,k) in a level with half-width H
@@ -199,10 +213,11 @@ int launch_apply(poisson_ctx &c, int mode, bool res, int nd, const T *x, T *y, c
     const int sb = sparse_blocks(nsp);
     const int gb = L.geo.nb;
 #define AP(MODE, RES, ND)                                                                                        \
-    k0_apply<T, MODE, RES, ND><<<gb, TPB, 0, s>>>(L.lv, L.geo, c.pin, x, y, b, sink, u1, u2, P, PSTRIDE);      \
+    k0_apply2<T, MODE, RES, ND><<<gb, TPB, 0, s>>>(L.lv, L.geo, c.pin, x, y, b, sink, u1, u2, P, PSTRIDE);     \
     if (nsp) k0_sparse<T, RES, ND><<<sb, TPB, 0, s>>>(L.lv, c.sp, x, y, b, u1, u2, P, PSTRIDE, gb);
     if (res) {
         if (mode == M_PINNED && nd == 2) { AP(M_PINNED, true, 2) }
+        else if (mode == M_UNPINNED && nd == 0) { AP(M_UNPINNED, true, 0) }
         else throw Error(IBM_EINVAL, "apply variant");
     } else {
         if (mode == M_PINZERO && nd == 1) { AP(M_PINZERO, false, 1) }
@@ -241,19 +256,27 @@ void fine_smooth(poisson_ctx &c, T *x, const T *b, const double *sink, bool from
     const int mb = sparse_blocks(c.nm), gb = sparse_blocks(c.nrows);
     for (int color = 0; color < 2; ++color) {
         if (from_zero && color == 0) {
-            k_sweep<true, T, T, 1><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, c.pin, x, b, sink, 0, c.nm > 0 ? 1 : 0);
+            // the other colour is zeroed too: ghost rows and membrane rows read it before its sweep
+            const long long pin_s = c.pin < L.Nh ? c.pin : -1;
+            k0_sweep_zero<T><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, pin_s, x, x + L.Nh, b, L.lv.f, sink, 0);
             if (c.nm) {
                 Walk Wt = make_walk(c.nm);
                 k_fill<T><<<Wt.nb, TPB, 0, s>>>(Wt, x + c.N2, 0.0);
             }
-        } else if (from_zero) {
-            k_sweep<true, T, T, 2><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, c.pin, x, b, sink, 1);
         } else {
-            prof_begin(c, PK_SWEEP0, s);
-            k_sweep<true, T, T, 0><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, c.pin, x, b, sink, color);
-            prof_end(c, PK_SWEEP0, s);
+            // (from zero, the black slots were zeroed by the red sweep; ghost
+            // values set since then must survive, so this is an ordinary sweep)
+            const long long co = (long long)color * L.Nh;
+            const long long pin_s = (c.pin >= co && c.pin < co + L.Nh) ? c.pin - co : -1;
+            if (!from_zero) prof_begin(c, PK_SWEEP0, s);
+            k0_sweep<T><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, pin_s, x + co, x + (L.Nh - co), b + co, L.lv.f + co,
+                                                 sink, color);
+            if (!from_zero) prof_end(c, PK_SWEEP0, s);
         }
-        if (c.nm) k0_msweep<T><<<mb, TPB, 0, s>>>(L.lv, c.sp, x, b, color);
+        if (c.nm) {
+            k0_msweep<T><<<mb, TPB, 0, s>>>(L.lv, c.sp, x, b, color, c.gtmp.p);
+            k0_mscat<T><<<mb, TPB, 0, s>>>(c.sp, x, color, c.gtmp.p);
+        }
         if (c.nrows) {
             k0_gjac<T><<<gb, TPB, 0, s>>>(c.sp, x, b, c.gtmp.p);
             k0_gscat<T><<<gb, TPB, 0, s>>>(c.sp, x, c.gtmp.p);
@@ -269,11 +292,11 @@ void coarse_smooth(Level &L, int steps, bool from_zero, const double *mean, hipS
     const TB *b = Store<Tc>::b(L);
     for (int it = 0; it < steps; ++it) {
         if (it == 0 && from_zero) {
-            k_sweep<false, Tc, TB, 1><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, -1, x, b, mean, 0);
-            k_sweep<false, Tc, TB, 2><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, -1, x, b, mean, 1);
+            k_csweep<Tc, TB, 1><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, x, b, mean, 0);
+            k_csweep<Tc, TB, 2><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, x, b, mean, 1);
         } else {
-            k_sweep<false, Tc, TB, 0><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, -1, x, b, mean, 0);
-            k_sweep<false, Tc, TB, 0><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, -1, x, b, mean, 1);
+            k_csweep<Tc, TB, 0><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, x, b, mean, 0);
+            k_csweep<Tc, TB, 0><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, x, b, mean, 1);
         }
     }
     IBM_LAUNCH_CHECK();
@@ -289,14 +312,16 @@ void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
     const poisson_opts &o = c.opts;
     for (int it = 0; it < o.nu1; ++it) fine_smooth<T>(c, x, b, sink, it == 0, s);
     if (nl > 1) {
-        T *rsp = std::is_same<T, double>::value ? (T *)c.rsp.p : (T *)c.frsp.p;
+        // level-0 residual: the sparse rows into r0, then the regular rows
+        // computed and restricted in one pass
+        T *r0 = std::is_same<T, double>::value ? (T *)c.rsp.p : (T *)c.frsp.p;
         const int nsp = (int)(c.nrows + c.nm);
-        if (nsp) k0_sparse_res<T><<<sparse_blocks(nsp), TPB, 0, s>>>(c.lv[0].lv, c.sp, x, b, rsp);
+        if (nsp) k0_sparse_res<T><<<sparse_blocks(nsp), TPB, 0, s>>>(c.lv[0].lv, c.sp, x, b, r0);
         Level &L1 = c.lv[1];
-        k_restrict<true, T, T, TB><<<L1.geo.nb, TPB, 0, s>>>(c.lv[0].lv, L1.lv, L1.geo, c.pin, x, b, sink, rsp,
-                                                            Store<T>::b(L1), c.part.p);
+        k0_restrict_res<T, TB><<<L1.geon.nb, TPB, 0, s>>>(c.lv[0].lv, L1.lv, L1.geon, c.pin, x, b, sink, r0,
+                                                         Store<T>::b(L1), c.part.p);
         IBM_LAUNCH_CHECK();
-        fin(c, L1.geo.nb, FIN_MEAN, S_MEAN0 + 1, L1.volA, s);
+        fin(c, L1.geon.nb, FIN_MEAN, S_MEAN0 + 1, L1.volA, s);
         const int lt = c.tail0;
         for (int l = 1; l < lt; ++l) {
             Level &L = c.lv[l];
@@ -307,11 +332,11 @@ void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
             }
             coarse_smooth<Tc, TB>(L, o.nu1, true, mean, s);
             Level &C = c.lv[l + 1];
-            k_restrict<false, Tc, TB, TB><<<C.geo.nb, TPB, 0, s>>>(L.lv, C.lv, C.geo, -1, Store<T>::x(L),
-                                                                  Store<T>::b(L), mean, (const Tc *)nullptr,
-                                                                  Store<T>::b(C), c.part.p);
+            k_restrict<false, Tc, TB, TB><<<C.geon.nb, TPB, 0, s>>>(L.lv, C.lv, C.geon, -1, Store<T>::x(L),
+                                                                   Store<T>::b(L), mean, (const Tc *)nullptr,
+                                                                   Store<T>::b(C), c.part.p);
             IBM_LAUNCH_CHECK();
-            fin(c, C.geo.nb, FIN_MEAN, S_MEAN0 + l + 1, C.volA, s);
+            fin(c, C.geon.nb, FIN_MEAN, S_MEAN0 + l + 1, C.volA, s);
         }
         if (lt < nl) {
             Tail tl;
@@ -319,26 +344,35 @@ void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
             tl.nu1 = o.nu1;
             tl.nu2 = o.nu2;
             tl.ncs = o.coarse_sweeps;
+            int off = 0;
             for (int q = 0; q < tl.n; ++q) {
                 Level &L = c.lv[lt + q];
                 tl.t[q].L = L.lv;
                 tl.t[q].M = L.pm;
                 tl.t[q].volA = L.volA;
-                tl.t[q].x = Store<T>::x(L);
-                tl.t[q].b = Store<T>::b(L);
-                tl.t[q].r = nullptr;
+                tl.t[q].xg = Store<T>::x(L);
+                tl.t[q].bg = Store<T>::b(L);
+                tail_layout(L.Nh, sizeof(Tc), off, tl.t[q].moff, tl.t[q].xoff, tl.t[q].boff);
             }
-            k_tail<Tc, TB><<<1, TAIL_T, 0, s>>>(tl, c.sc.p + S_MEAN0 + lt);
+            k_tail<Tc, TB><<<1, TAIL_T, off, s>>>(tl, c.sc.p + S_MEAN0 + lt);
             IBM_LAUNCH_CHECK();
         }
         for (int l = std::min(lt, nl - 1) - 1; l >= 1; --l) {
             Level &L = c.lv[l];
             Level &C = c.lv[l + 1];
-            k_prolong<false, Tc, Tc><<<L.geo.nb, TPB, 0, s>>>(L.lv, C.lv, L.pm, L.geo, Store<T>::x(C), Store<T>::x(L));
+            if (o.nu2 > 0)
+                k_prolong_z<false, Tc, Tc, true><<<C.geon.nb, TPB, 0, s>>>(L.lv, C.lv, L.pm, C.geon, Store<T>::x(C),
+                                                                           Store<T>::x(L));
+            else
+                k_prolong_z<false, Tc, Tc, false><<<C.geon.nb, TPB, 0, s>>>(L.lv, C.lv, L.pm, C.geon, Store<T>::x(C),
+                                                                            Store<T>::x(L));
             coarse_smooth<Tc, TB>(L, o.nu2, false, c.sc.p + S_MEAN0 + l, s);
         }
         Level &L0v = c.lv[0];
-        k_prolong<true, Tc, T><<<L0v.geo.nb, TPB, 0, s>>>(L0v.lv, L1.lv, L0v.pm, L0v.geo, Store<T>::x(L1), x);
+        if (o.nu2 > 0)
+            k_prolong_z<true, Tc, T, true><<<L1.geon.nb, TPB, 0, s>>>(L0v.lv, L1.lv, L0v.pm, L1.geon, Store<T>::x(L1), x);
+        else
+            k_prolong_z<true, Tc, T, false><<<L1.geon.nb, TPB, 0, s>>>(L0v.lv, L1.lv, L0v.pm, L1.geon, Store<T>::x(L1), x);
         IBM_LAUNCH_CHECK();
     }
     for (int it = 0; it < o.nu2; ++it) fine_smooth<T>(c, x, b, sink, false, s);
@@ -698,12 +732,19 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
                             C.hm[P] |= (uint8_t)(2 << d);
                 }
         C.volA = va;
+        // device mask: active and +faces from hm, -faces copied from the
+        // neighbour's +face bit (hm keeps the cut bits for the next level)
         std::vector<uint8_t> sm(2 * C.Nh, 0);
         for (int K = 0; K < C.n[2]; ++K)
             for (int J = 0; J < C.n[1]; ++J)
-                for (int I = 0; I < C.n[0]; ++I)
-                    sm[host_slot(C.H, C.n[1], C.Nh, I, J, K)] =
-                        C.hm[I + (long long)C.n[0] * (J + (long long)C.n[1] * K)] & 15;
+                for (int I = 0; I < C.n[0]; ++I) {
+                    const long long P = I + (long long)C.n[0] * (J + (long long)C.n[1] * K);
+                    uint8_t m = C.hm[P] & 15;
+                    if (I > 0 && (C.hm[P - 1] & 2)) m |= 16;
+                    if (J > 0 && (C.hm[P - C.n[0]] & 4)) m |= 32;
+                    if (K > 0 && (C.hm[P - (long long)C.n[0] * C.n[1]] & 8)) m |= 64;
+                    sm[host_slot(C.H, C.n[1], C.Nh, I, J, K)] = m;
+                }
         upload(C.m, sm, s);
         // prolongation maps of F from C
         for (int d = 0; d < 3; ++d) {
@@ -724,7 +765,17 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
     }
     // device views, coarse storage, tail start
     c->tail0 = nl;
-    for (int l = nl - 1; l >= 1 && c->lv[l].N <= TAIL_MAX && (nl - l) <= 8; --l) c->tail0 = l;
+    {
+        const size_t tsz = c->mixed ? sizeof(float) : sizeof(double);
+        int off = 0;
+        for (int l = nl - 1; l >= 1 && (nl - l) <= 8; --l) {
+            int m, xo, bo, o2 = off;
+            tail_layout(c->lv[l].Nh, tsz, o2, m, xo, bo);
+            if (o2 > TAIL_LDS) break;
+            off = o2;
+            c->tail0 = l;
+        }
+    }
     for (int l = 0; l < nl; ++l) {
         Level &L = c->lv[l];
         Lv &v = L.lv;
@@ -767,7 +818,7 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
     c->bytes = estimate_bytes(nx, ny, nz, c->nrows, o.precision);
     for (auto &L : c->lv) { L.hm.clear(); L.hm.shrink_to_fit(); }
     IBM_REQUIRE(c->lv[0].geo.nb <= PSTRIDE - 2048 && c->W0.nb <= PSTRIDE - 2048, IBM_EINVAL, "grid too large");
-    for (auto &L : c->lv) IBM_REQUIRE(L.geo.nb <= PSTRIDE, IBM_EINVAL, "grid too large");
+    for (auto &L : c->lv) IBM_REQUIRE(L.geo.nb <= PSTRIDE && L.geon.nb <= PSTRIDE, IBM_EINVAL, "grid too large");
     return c.release();
 }
 
@@ -884,7 +935,7 @@ extern "C" void poisson_default_opts(poisson_opts *o)
     o->nu1 = 2;
     o->nu2 = 2;
     o->coarse_sweeps = 32;
-    o->inner_tol = 1e-4;
+    o->inner_tol = 1e-3;
     o->max_outer = 10;
     o->use_graph = 1;
 }
