@@ -118,7 +118,7 @@ inline Geo make_geo(int H, int ny, int nz)
     g.gy = (ny + 3) / 4;
     long long xy = (long long)g.gx * g.gy;
     int kz = 1;
-    while (xy * ((nz + kz - 1) / kz) > 8192 && kz < nz) kz *= 2;
+    while (xy * ((nz + kz - 1) / kz) > 16384 && kz < nz) kz *= 2;
     g.kz = kz;
     g.gz = (nz + kz - 1) / kz;
     long long n = xy * g.gz;
@@ -571,28 +571,44 @@ __global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, con
         const long long pl = (long long)L.H * L.ny, Nh = L.Nh;
         const long long col = h + (long long)L.H * j;
         const Col0 q0 = col0(L, 0, h, j), q1 = col0(L, 1, h, j);
-        for (int k = k0; k < k1; ++k) {
-            const long long s = col + pl * k, t = Nh + s;
-            const uint8_t f0 = L.f[s], f1 = L.f[t];
-            const double x0 = ld(x, s), x1 = ld(x, t);
-            double d0, d1;
-            const double n0 = col0_sum(L, q0, x + Nh, s, k, pl, d0);
-            const double n1 = col0_sum(L, q1, x, s, k, pl, d1);
-            const double b0 = RES ? ld(b, s) : 0.0, b1 = RES ? ld(b, t) : 0.0;
-            const double v0 = ND >= 1 ? ld(u1, s) : 0.0, v1 = ND >= 1 ? ld(u1, t) : 0.0;
-            const double w0 = (ND >= 2 && u2) ? ld(u2, s) : 0.0, w1 = (ND >= 2 && u2) ? ld(u2, t) : 0.0;
-            double o;
-            if (apply_out<T, MODE, RES>(f0, x0, n0, d0, b0, s, pin, sink, o)) {
-                st(y, s, o);
-                const double yo = ld(y, s);
-                if (ND >= 1) a0 += v0 * yo;
-                if (ND >= 2) a1 += (u2 ? w0 : yo) * yo;
+        // UA planes per step; every load of a step is issued before any store
+        constexpr int UA = 2;
+        for (int kb = k0; kb < k1; kb += UA) {
+            uint8_t f[UA][2];
+            double xv[UA][2], nb[UA][2], dg[UA][2], bv[UA][2], u1v[UA][2], u2v[UA][2];
+#pragma unroll
+            for (int u = 0; u < UA; ++u) {
+                const int k = min(kb + u, k1 - 1);
+                const long long s = col + pl * k, t = Nh + s;
+                f[u][0] = L.f[s];
+                f[u][1] = L.f[t];
+                xv[u][0] = ld(x, s);
+                xv[u][1] = ld(x, t);
+                nb[u][0] = col0_sum(L, q0, x + Nh, s, k, pl, dg[u][0]);
+                nb[u][1] = col0_sum(L, q1, x, s, k, pl, dg[u][1]);
+                bv[u][0] = RES ? ld(b, s) : 0.0;
+                bv[u][1] = RES ? ld(b, t) : 0.0;
+                u1v[u][0] = ND >= 1 ? ld(u1, s) : 0.0;
+                u1v[u][1] = ND >= 1 ? ld(u1, t) : 0.0;
+                u2v[u][0] = (ND >= 2 && u2) ? ld(u2, s) : 0.0;
+                u2v[u][1] = (ND >= 2 && u2) ? ld(u2, t) : 0.0;
             }
-            if (apply_out<T, MODE, RES>(f1, x1, n1, d1, b1, t, pin, sink, o)) {
-                st(y, t, o);
-                const double yo = ld(y, t);
-                if (ND >= 1) a0 += v1 * yo;
-                if (ND >= 2) a1 += (u2 ? w1 : yo) * yo;
+#pragma unroll
+            for (int u = 0; u < UA; ++u) {
+                if (kb + u >= k1) continue;
+                const long long s0 = col + pl * (kb + u);
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    const long long sc = s0 + (cc ? Nh : 0);
+                    double o;
+                    if (apply_out<T, MODE, RES>(f[u][cc], xv[u][cc], nb[u][cc], dg[u][cc], bv[u][cc], sc, pin, sink,
+                                                o)) {
+                        st(y, sc, o);
+                        const double yo = round_to<T>(o);  // the stored value
+                        if (ND >= 1) a0 += u1v[u][cc] * yo;
+                        if (ND >= 2) a1 += (u2 ? u2v[u][cc] : yo) * yo;
+                    }
+                }
             }
         }
     }
@@ -794,13 +810,13 @@ __global__ void __launch_bounds__(TPB) k0_restrict_res(Lv F, Lv C, Geo Gc, long 
         const long long rowm = H * max(2 * J - 1, 0), row0 = H * (2 * J), row1 = H * (2 * J + 1),
                         rowp = H * min(2 * J + 2, F.ny - 1);
         // v[c][dy][q]: colour c, row 2J+dy, plane 2K-1+q
-        double v[2][2][4];
+        T v[2][2][4];
         auto ldcol = [&](int kk, int q) {
             const long long z = pl * min(max(kk, 0), F.nz - 1);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                v[c][0][q] = ld(x, c * Nh + I + row0 + z);
-                v[c][1][q] = ld(x, c * Nh + I + row1 + z);
+                v[c][0][q] = x[c * Nh + I + row0 + z];
+                v[c][1][q] = x[c * Nh + I + row1 + z];
             }
         };
         ldcol(2 * k0 - 1, 0);
@@ -808,33 +824,46 @@ __global__ void __launch_bounds__(TPB) k0_restrict_res(Lv F, Lv C, Geo Gc, long 
         for (int K = k0; K < k1; ++K) {
             ldcol(2 * K + 1, 2);
             ldcol(2 * K + 2, 3);
+            // every load of the step is issued before any use: flags, RHS,
+            // the outer x and y neighbours of the 8 children
+            uint8_t fq[8];
+            T bq[8], xq[8], yq[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+                const int c = (dx + dy + dz) & 1, o = 1 - c;
+                const long long zk = pl * (2 * K + dz);
+                const long long s = c * Nh + I + (dy ? row1 : row0) + zk;
+                fq[q] = F.f[s];
+                bq[q] = b[s];
+                xq[q] = x[o * Nh + (dx ? hp : hm) + (dy ? row1 : row0) + zk];
+                yq[q] = x[o * Nh + I + (dy ? rowp : rowm) + zk];
+            }
             double sv = 0.0, svr = 0.0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
                 const int c = (dx + dy + dz) & 1, o = 1 - c;
                 const int k = 2 * K + dz;
-                const long long zk = pl * k;
-                const long long s = c * Nh + I + (dy ? row1 : row0) + zk;
-                const uint8_t f = F.f[s];
+                const uint8_t f = fq[q];
                 if (!active0(f)) continue;
                 double r;
                 if (f & (F_GHOST | F_MGHOST)) {
-                    r = ld(rsp, s);
+                    r = ld(rsp, c * Nh + I + (dy ? row1 : row0) + pl * k);
                 } else {
                     const double xv = v[c][dy][1 + dz];
                     const double xin = v[o][dy][1 + dz];
-                    const double xout = ld(x, o * Nh + (dx ? hp : hm) + (dy ? row1 : row0) + zk);
+                    const double xout = xq[q];
                     const double xpx = dx ? xout : xin, xmx = dx ? xin : xout;
-                    const double xpy = dy ? ld(x, o * Nh + I + rowp + zk) : v[o][1][1 + dz];
-                    const double xmy = dy ? v[o][0][1 + dz] : ld(x, o * Nh + I + rowm + zk);
+                    const double xpy = dy ? (double)yq[q] : (double)v[o][1][1 + dz];
+                    const double xmy = dy ? (double)v[o][0][1 + dz] : (double)yq[q];
                     const double xpz = v[o][dy][2 + dz], xmz = v[o][dy][dz];
                     const double czp = F.cp[2][k], czm = F.cm[2][k];  // zero at the walls
                     const double dg = cpx[dx] + cmx[dx] + cpy[dy] + cmy[dy] + czp + czm;
                     const double n = cpx[dx] * xpx + cmx[dx] * xmx + cpy[dy] * xpy + cmy[dy] * xmy + czp * xpz +
                                      czm * xmz;
-                    double bv = ld(b, s);
-                    if (s == pin) bv -= snk;
+                    double bv = bq[q];
+                    if (c * Nh + I + (dy ? row1 : row0) + pl * k == pin) bv -= snk;
                     r = bv - (n - dg * xv);
                 }
                 const double V = wx[dx] * wy[dy] * F.w[2][k];
@@ -937,6 +966,18 @@ __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, c
     plane(k0, vb);
     for (int K = k0; K < k1; ++K) {
         plane(min(K + 1, C.nz - 1), vn);
+        // flags of the 8 children and the values to be corrected, issued
+        // together (red values only when they are corrected at all)
+        uint8_t fq[8];
+        Tf xq[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+            const int cf = (dx + dy + dz) & 1;
+            const long long s = (long long)cf * F.Nh + I + (long long)F.H * (2 * J + dy) + fpl * (2 * K + dz);
+            fq[q] = F.f[s];
+            if (!SKIP_RED || cf == 1) xq[q] = xf[s];
+        }
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz) {
             const int k = 2 * K + dz;
@@ -958,13 +999,20 @@ __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, c
                                    : (1 - ty[dy]) * zz[0][e] + ty[dy] * zz[1][e];
 #pragma unroll
                 for (int dx = 0; dx < 2; ++dx) {
+                    const int q = dx + 2 * dy + 4 * dz;
                     const int cf = (dx + dy + dz) & 1;
                     const long long s = (long long)cf * F.Nh + I + (long long)F.H * (2 * J + dy) + fpl * k;
-                    const uint8_t f = F.f[s];
+                    const uint8_t f = fq[q];
                     if (FINE ? !active0(f) : !(f & 1)) continue;
-                    if (SKIP_RED && cf == 0 && (!FINE || !(f & (F_GHOST | F_MGHOST)))) continue;
+                    Tf xv;
+                    if (SKIP_RED && cf == 0) {
+                        if (!FINE || !(f & (F_GHOST | F_MGHOST))) continue;
+                        xv = xf[s];
+                    } else {
+                        xv = xq[q];
+                    }
                     const R val = ex[dx] ? (1 - tx[dx]) * yy[1] + tx[dx] * yy[2] : (1 - tx[dx]) * yy[0] + tx[dx] * yy[1];
-                    st(xf, s, ld(xf, s) + val);
+                    xf[s] = (Tf)((R)xv + val);
                 }
             }
         }
@@ -1154,21 +1202,95 @@ __device__ __forceinline__ double slot_volume(const Lv &L, long long s, bool &ac
     return act ? L.w[0][i] * L.w[1][j] * L.w[2][k] : 0.0;
 }
 
-// p = r + beta (p - omega v); partial sum of V p over active cells (sink)
+// ---------------------------------------------------------------- 4-wide vector walks
+// The Krylov updates walk groups of 4 consecutive unknowns (one 16-byte load
+// per FP32 vector, two per FP64 vector); a group that is cut by the end of
+// the vector or by the first membrane unknown takes the element path.
+__device__ __forceinline__ void ld4(const float *a, long long g, double (&o)[4])
+{
+    const float4 q = reinterpret_cast<const float4 *>(a)[g];
+    o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+}
+__device__ __forceinline__ void ld4(const double *a, long long g, double (&o)[4])
+{
+    const double2 q0 = reinterpret_cast<const double2 *>(a)[2 * g], q1 = reinterpret_cast<const double2 *>(a)[2 * g + 1];
+    o[0] = q0.x; o[1] = q0.y; o[2] = q1.x; o[3] = q1.y;
+}
+__device__ __forceinline__ void st4(float *a, long long g, double (&o)[4])
+{
+    float4 q;
+    q.x = (float)o[0]; q.y = (float)o[1]; q.z = (float)o[2]; q.w = (float)o[3];
+    reinterpret_cast<float4 *>(a)[g] = q;
+    o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;  // the stored (rounded) values
+}
+__device__ __forceinline__ void st4(double *a, long long g, double (&o)[4])
+{
+    double2 q0, q1;
+    q0.x = o[0]; q0.y = o[1]; q1.x = o[2]; q1.y = o[3];
+    reinterpret_cast<double2 *>(a)[2 * g] = q0;
+    reinterpret_cast<double2 *>(a)[2 * g + 1] = q1;
+}
+
+// volumes of the 4 cells of a group (0 for inactive slots); e0 + 3 < 2 Nh
+__device__ __forceinline__ void group_volumes(const Lv &L, long long e0, double (&V)[4])
+{
+    const uchar4 fq = *reinterpret_cast<const uchar4 *>(L.f + e0);
+    const uint8_t f[4] = {fq.x, fq.y, fq.z, fq.w};
+    int c, h, j, k, i;
+    decode_slot(L, e0, c, h, j, k, i);
+    if (h + 3 < L.H) {
+        const double wjk = L.w[1][j] * L.w[2][k];
+        const int par = i & 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int iq = 2 * (h + q) + par;
+            V[q] = (iq < L.nx && active0(f[q])) ? L.w[0][iq] * wjk : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bool act;
+            V[q] = slot_volume(L, e0 + q, act);
+        }
+    }
+}
+
+// p = r + beta (p - omega v); partial sum of V p over the active cells (the
+// sink of the first V-cycle).  ne unknowns, W over ceil(ne/4) groups.
 template <class T>
-__global__ void __launch_bounds__(TPB) k_p_update(Lv L, Walk W, const T *r, T *pv, const T *v, const double *sc,
-                                                  double *part)
+__global__ void __launch_bounds__(TPB) k_p_update4(Lv L, Walk W, long long ne, const T *__restrict__ r,
+                                                   T *__restrict__ pv, const T *__restrict__ v, const double *sc,
+                                                   double *part)
 {
     const double beta = sc[S_BETA], omega = sc[S_OMEGA];
     Acc<1> a;
     a.v[0] = 0.0;
     const long long N2 = 2 * L.Nh;
-    WALK_BEGIN(W, p)
-        st(pv, p, ld(r, p) + beta * (ld(pv, p) - omega * ld(v, p)));
-        if (p < N2) {
-            bool act;
-            const double V = slot_volume(L, p, act);
-            if (act) a.v[0] += V * ld(pv, p);
+    WALK_BEGIN(W, g)
+        const long long e0 = 4 * g;
+        if (e0 + 3 < ne && (e0 + 3 < N2 || e0 >= N2)) {
+            double rr[4], pp[4], vv[4];
+            ld4(r, g, rr);
+            ld4(pv, g, pp);
+            ld4(v, g, vv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pp[q] = rr[q] + beta * (pp[q] - omega * vv[q]);
+            st4(pv, g, pp);
+            if (e0 < N2) {
+                double V[4];
+                group_volumes(L, e0, V);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a.v[0] += V[q] * pp[q];
+            }
+        } else {
+            for (long long p = e0; p < min(e0 + 4, ne); ++p) {
+                st(pv, p, ld(r, p) + beta * (ld(pv, p) - omega * ld(v, p)));
+                if (p < N2) {
+                    bool act;
+                    const double V = slot_volume(L, p, act);
+                    if (act) a.v[0] += V * ld(pv, p);
+                }
+            }
         }
     WALK_END
     block_reduce<1>(a, part, 0, blockIdx.x);
@@ -1176,18 +1298,37 @@ __global__ void __launch_bounds__(TPB) k_p_update(Lv L, Walk W, const T *r, T *p
 
 // r <- s = r - alpha v; partial sum of V s (sink of the second V-cycle)
 template <class T>
-__global__ void __launch_bounds__(TPB) k_s_update(Lv L, Walk W, T *r, const T *v, const double *sc, double *part)
+__global__ void __launch_bounds__(TPB) k_s_update4(Lv L, Walk W, long long ne, T *__restrict__ r,
+                                                   const T *__restrict__ v, const double *sc, double *part)
 {
     const double alpha = sc[S_ALPHA];
     Acc<1> a;
     a.v[0] = 0.0;
     const long long N2 = 2 * L.Nh;
-    WALK_BEGIN(W, p)
-        st(r, p, ld(r, p) - alpha * ld(v, p));
-        if (p < N2) {
-            bool act;
-            const double V = slot_volume(L, p, act);
-            if (act) a.v[0] += V * ld(r, p);
+    WALK_BEGIN(W, g)
+        const long long e0 = 4 * g;
+        if (e0 + 3 < ne && (e0 + 3 < N2 || e0 >= N2)) {
+            double rr[4], vv[4];
+            ld4(r, g, rr);
+            ld4(v, g, vv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rr[q] = rr[q] - alpha * vv[q];
+            st4(r, g, rr);
+            if (e0 < N2) {
+                double V[4];
+                group_volumes(L, e0, V);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a.v[0] += V[q] * rr[q];
+            }
+        } else {
+            for (long long p = e0; p < min(e0 + 4, ne); ++p) {
+                st(r, p, ld(r, p) - alpha * ld(v, p));
+                if (p < N2) {
+                    bool act;
+                    const double V = slot_volume(L, p, act);
+                    if (act) a.v[0] += V * ld(r, p);
+                }
+            }
         }
     WALK_END
     block_reduce<1>(a, part, 0, blockIdx.x);
@@ -1197,22 +1338,54 @@ __global__ void __launch_bounds__(TPB) k_s_update(Lv L, Walk W, T *r, const T *v
 // preconditioner's shift to the pinned subspace, folded in here); r = s -
 // omega t; partials of (rh, r) and (r, r)
 template <class T, class TX>
-__global__ void __launch_bounds__(TPB) k_xr_update(Lv L, Walk W, long long pin, TX *x, const T *ph, const T *sh,
-                                                   T *r, const T *t, const T *rh, const double *sc, double *part,
-                                                   int pstride)
+__global__ void __launch_bounds__(TPB) k_xr_update4(Lv L, Walk W, long long ne, long long pin, TX *__restrict__ x,
+                                                    const T *__restrict__ ph, const T *__restrict__ sh,
+                                                    T *__restrict__ r, const T *__restrict__ t,
+                                                    const T *__restrict__ rh, const double *sc, double *part,
+                                                    int pstride)
 {
     const double alpha = sc[S_ALPHA], omega = sc[S_OMEGA];
     const double cp = ld(ph, pin), cs = ld(sh, pin);
     const long long N2 = 2 * L.Nh;
     Acc<2> a;
     a.v[0] = a.v[1] = 0.0;
-    WALK_BEGIN(W, p)
-        const bool act = p >= N2 || active0(L.f[p]);
-        if (act) st(x, p, ld(x, p) + alpha * (ld(ph, p) - cp) + omega * (ld(sh, p) - cs));
-        st(r, p, ld(r, p) - omega * ld(t, p));
-        const double rv = ld(r, p);
-        a.v[0] += ld(rh, p) * rv;
-        a.v[1] += rv * rv;
+    WALK_BEGIN(W, g)
+        const long long e0 = 4 * g;
+        if (e0 + 3 < ne && (e0 + 3 < N2 || e0 >= N2)) {
+            double xx[4], pp[4], ss[4], rr[4], tt[4], hh[4];
+            ld4(x, g, xx);
+            ld4(ph, g, pp);
+            ld4(sh, g, ss);
+            ld4(r, g, rr);
+            ld4(t, g, tt);
+            ld4(rh, g, hh);
+            bool act[4] = {true, true, true, true};
+            if (e0 < N2) {
+                const uchar4 fq = *reinterpret_cast<const uchar4 *>(L.f + e0);
+                act[0] = active0(fq.x); act[1] = active0(fq.y); act[2] = active0(fq.z); act[3] = active0(fq.w);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (act[q]) xx[q] = xx[q] + alpha * (pp[q] - cp) + omega * (ss[q] - cs);
+                rr[q] = rr[q] - omega * tt[q];
+            }
+            st4(x, g, xx);
+            st4(r, g, rr);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a.v[0] += hh[q] * rr[q];
+                a.v[1] += rr[q] * rr[q];
+            }
+        } else {
+            for (long long p = e0; p < min(e0 + 4, ne); ++p) {
+                const bool act = p >= N2 || active0(L.f[p]);
+                if (act) st(x, p, ld(x, p) + alpha * (ld(ph, p) - cp) + omega * (ld(sh, p) - cs));
+                st(r, p, ld(r, p) - omega * ld(t, p));
+                const double rv = ld(r, p);
+                a.v[0] += ld(rh, p) * rv;
+                a.v[1] += rv * rv;
+            }
+        }
     WALK_END
     block_reduce<2>(a, part, pstride, blockIdx.x);
 }

@@ -115,6 +115,7 @@ struct poisson_ctx {
     std::vector<Level> lv;
     Sp sp;
     Walk W0;   // over Nt unknowns
+    Walk W4;   // over ceil(Nt / 4) groups of 4 unknowns
     Walk Wc;   // over 2 Nh cell slots
     DBuf<double> x, r, rh, p, v, ph, sh, t, rsp, b;
     DBuf<float> fd, fr, frh, fp, fv, fph, fsh, ft, frsp;
@@ -383,22 +384,23 @@ void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
 template <class T>
 void bicg_iteration(poisson_ctx &c, T *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, hipStream_t s)
 {
-    const Walk &W = c.W0;
+    const Walk &W = c.W4;
     const Lv &L = c.L0();
-    k_p_update<T><<<W.nb, TPB, 0, s>>>(L, W, r, p, v, c.sc.p, c.part.p);
+    k_p_update4<T><<<W.nb, TPB, 0, s>>>(L, W, c.Nt, r, p, v, c.sc.p, c.part.p);
     fin(c, W.nb, FIN_SINK, S_SINKP, 0.0, s);
     vcycle<T>(c, p, ph, c.sc.p + S_SINKP, s);
     prof_begin(c, PK_APPLY0, s);
     int np = launch_apply<T>(c, M_PINZERO, false, 1, ph, v, nullptr, nullptr, rh, nullptr, s);
     prof_end(c, PK_APPLY0, s);
     fin(c, np, FIN_ALPHA, 0, 0.0, s);
-    k_s_update<T><<<W.nb, TPB, 0, s>>>(L, W, r, v, c.sc.p, c.part.p);
+    k_s_update4<T><<<W.nb, TPB, 0, s>>>(L, W, c.Nt, r, v, c.sc.p, c.part.p);
     fin(c, W.nb, FIN_SINK, S_SINKS, 0.0, s);
     vcycle<T>(c, r, sh, c.sc.p + S_SINKS, s);
     np = launch_apply<T>(c, M_PINZERO, false, 2, sh, t, nullptr, nullptr, r, nullptr, s);
     fin(c, np, FIN_OMEGA, 0, 0.0, s);
     prof_begin(c, PK_XR, s);
-    k_xr_update<T, T><<<W.nb, TPB, 0, s>>>(L, W, c.pin, y, ph, sh, r, t, rh, c.sc.p, c.part.p, PSTRIDE);
+    k_xr_update4<T, T><<<W.nb, TPB, 0, s>>>(L, W, c.Nt, c.pin, y, ph, sh, r, t, rh, c.sc.p, c.part.p,
+                                              PSTRIDE);
     prof_end(c, PK_XR, s);
     IBM_LAUNCH_CHECK();
     fin(c, W.nb, FIN_RHO, 0, 0.0, s);
@@ -799,6 +801,7 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
     S.nm = (int)c->nm;
     S.mslot = c->mslot.p; S.mcol = c->mcol.p; S.mcolor = c->mcolor.p;
     c->W0 = make_walk(c->Nt);
+    c->W4 = make_walk((c->Nt + 3) / 4);
     c->Wc = make_walk(c->N2);
     const long long Nt = c->Nt;
     c->x.alloc(Nt); c->r.alloc(Nt); c->b.alloc(Nt); c->t.alloc(Nt);
