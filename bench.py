@@ -56,6 +56,37 @@ def make_problem(cfg):
     raise SystemExit("unknown config " + cfg)
 
 
+def sweep_source_digest():
+    """Digest of the level-0 half-sweep kernel's source (its column helpers
+    and the kernel itself): HBM counters taken for another version of the
+    kernel do not describe this one."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2605_04335_amd", "csrc", "kernels.hpp")).read()
+    a = src.index("struct Col0 {")
+    b = src.index("// First level-0 half-sweep of a V-cycle, from a zero iterate")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def measured_traffic(workload_key):
+    """HBM bytes per launch of k0_sweep from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
+    the summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "k0_sweep_%s_traffic.md" % workload_key)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_digest") != sweep_source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(cfg, budget_s):
     """The FP64 oracle on a bounded sample of the same workload recipe."""
     import oracle
@@ -90,6 +121,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="finish with 3 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the PPE solve on a single MI355X; "
@@ -151,8 +184,10 @@ def main():
         # flag byte, write this colour's values
         bytes_launch = (1.5 * T + 0.5) * N
         ach = bytes_launch / (avg_ms * 1e-3) / 1e9
+        tr = measured_traffic({"c3": "membrane512", "c2": "spheroids256", "c4": "spheres1024",
+                               "c1": "sphere32"}[args.config])
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k0_sweep<float>",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": (int(tr) if tr else None), "kernel": "k0_sweep<float>",
                 "avg_launch_ms": round(avg_ms, 4), "launches_per_solve": cnt,
                 "algorithmic_bytes_per_launch": int(bytes_launch)}
 
@@ -186,6 +221,17 @@ def main():
         out["config"]["mixed_rel_error_vs_fp64"] = err
         log("fp64: %.1f ms/solve, %d its; mixed speed-up %.2fx, rel error %.2e" % (ms64, s64.iterations,
                                                                                    ms64 / ms_per_step, err))
+    if args.copy_calibration:
+        import torch as _t
+        nbytes = 1 << 30
+        src = _t.ones(nbytes, dtype=_t.uint8, device=dev)
+        dst = _t.empty_like(src)
+        _t.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        _t.cuda.synchronize()
+        log("copy calibration: 3 device-to-device copies of %d bytes" % nbytes)
+        del src, dst
     if rank == 0 and not args.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(args.config, 30)

@@ -110,7 +110,7 @@ struct Geo {
     int nb;          // launched blocks (multiple of 8, >= gx*gy*gz)
     int H, ny, nz;
 };
-inline Geo make_geo(int H, int ny, int nz)
+inline Geo make_geo(int H, int ny, int nz, int maxb = 8192)
 {
     Geo g;
     g.H = H; g.ny = ny; g.nz = nz;
@@ -118,7 +118,7 @@ inline Geo make_geo(int H, int ny, int nz)
     g.gy = (ny + 3) / 4;
     long long xy = (long long)g.gx * g.gy;
     int kz = 1;
-    while (xy * ((nz + kz - 1) / kz) > 16384 && kz < nz) kz *= 2;
+    while (xy * ((nz + kz - 1) / kz) > maxb && kz < nz) kz *= 2;
     g.kz = kz;
     g.gz = (nz + kz - 1) / kz;
     long long n = xy * g.gz;

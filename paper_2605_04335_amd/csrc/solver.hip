@@ -615,6 +615,8 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
             }
         level_geometry(L, faces, s);
     }
+    // level 0: shorter plane runs per thread (more tiles) measured faster
+    c->lv[0].geo = make_geo(c->lv[0].H, c->lv[0].n[1], c->lv[0].n[2], 16384);
     Level &Z = c->lv[0];
     c->N2 = 2 * Z.Nh;
     c->Nt = c->N2 + c->nm;
