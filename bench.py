@@ -87,6 +87,55 @@ def measured_traffic(workload_key):
         return None
 
 
+def serving_bench(P, rates, nreq, seed=5, slots=4, budget=64 << 30):
+    """Poisson arrivals of mixed-precision solve requests (grid edge
+    log-uniform in [64, 384], cube or 2:1:1, 1-4 bodies, tol 1e-8) into the
+    continuous-batching server; latency = done - submit on the server clock."""
+    from paper_2605_04335_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for q in range(nreq):
+        p = W.serving_request(rng)
+        p.f = W.noise_rhs(p.npts, seed + 1000 + q)
+        reqs.append(p)
+    # one warm-up request outside the measurement (first-use costs of the runtime)
+    srv = P.Server(hbm_budget=budget, max_slots=slots)
+    t = srv.submit(reqs[0].xf, reqs[0].yf, reqs[0].zf, reqs[0].bodies, reqs[0].f, precision="mixed", tol=1e-8)
+    while srv.poll(t, want_x=False)[0] == P.IBM_EAGAIN:
+        time.sleep(0.001)
+    out = []
+    for rate in rates:
+        arr = np.cumsum(np.random.default_rng(seed + int(rate)).exponential(1.0 / rate, nreq))
+        pending, done = {}, []
+        t0 = time.perf_counter()
+        q = 0
+        while q < nreq or pending:
+            now = time.perf_counter() - t0
+            while q < nreq and arr[q] <= now:
+                p = reqs[q]
+                pending[srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, precision="mixed", tol=1e-8)] = p.npts
+                q += 1
+            for tk in list(pending):
+                rc, state, _, st, tm = srv.poll(tk, want_x=False)
+                if rc == P.IBM_EAGAIN:
+                    continue
+                done.append((tm.submit_ms, tm.done_ms, pending.pop(tk), rc, st.rel_residual))
+            time.sleep(0.0005)
+        lat = np.array([d[1] - d[0] for d in done])
+        span_s = (max(d[1] for d in done) - min(d[0] for d in done)) / 1e3
+        pts = sum(d[2] for d in done)
+        ok = sum(1 for d in done if d[3] == 0 and d[4] <= 1e-8)
+        out.append({"rate_req_s": rate, "requests": nreq, "ok": ok, "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 2), "solves_s": round(nreq / span_s, 2),
+                    "Mpts_s": round(pts / span_s / 1e6, 1)})
+        log("serve rate %g req/s: p50 %.1f ms p99 %.1f ms, %.1f solves/s, %.0f Mpts/s, %d/%d ok" %
+            (rate, out[-1]["p50_ms"], out[-1]["p99_ms"], out[-1]["solves_s"], out[-1]["Mpts_s"], ok, nreq))
+    srv.close()
+    return {"workload": "Poisson arrivals, edge log-uniform [64, 384], cube or 2:1:1, 1-4 bodies (spheres, "
+                        "ellipsoids, plates), noise RHS, mixed MG-BiCGSTAB to 1e-8",
+            "max_slots": slots, "hbm_budget_GB": budget >> 30, "sweep": out}
+
+
 def cpu_baseline(cfg, budget_s):
     """The FP64 oracle on a bounded sample of the same workload recipe."""
     import oracle
@@ -121,6 +170,9 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--serve-rates", default="5,20,80", help="request arrival rates (req/s) of the serving sweep")
+    ap.add_argument("--serve-requests", type=int, default=24, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with 3 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -221,6 +273,8 @@ def main():
         out["config"]["mixed_rel_error_vs_fp64"] = err
         log("fp64: %.1f ms/solve, %d its; mixed speed-up %.2fx, rel error %.2e" % (ms64, s64.iterations,
                                                                                    ms64 / ms_per_step, err))
+    if not args.no_serve:
+        out["serving"] = serving_bench(P, [float(r) for r in args.serve_rates.split(",")], args.serve_requests)
     if args.copy_calibration:
         import torch as _t
         nbytes = 1 << 30

@@ -212,10 +212,16 @@ void poisson_destroy(poisson_ctx *ctx);
 
 /* ------------------------------------------------------------------ serving
  * A persistent scheduler thread owns one device and runs many solves at
- * once (continuous batching at BiCGSTAB-iteration granularity, one stream
- * per active solve).  Requests are admitted while the number of active
- * solves is below max_slots and the summed footprints fit hbm_budget;
- * finished solves release their slot and memory at once.
+ * once (continuous batching: a request that arrives while others are on the
+ * GPU is admitted as soon as a slot and memory are free, and runs its whole
+ * pipeline -- classification, stencils, set-up, solve -- on its own stream,
+ * so its kernels interleave with those of the running solves).  Requests are
+ * admitted first come, first served while the number of active solves is
+ * below max_slots and the summed footprints (poisson_workspace_estimate plus
+ * classification temporaries) fit hbm_budget; a request larger than the
+ * whole budget fails with IBM_ENOMEM.  Finished solves release their slot and
+ * memory at once.  Every solve is deterministic, so a result is the same
+ * alone and in the mix.
  */
 typedef struct poisson_server poisson_server;
 
@@ -240,6 +246,7 @@ typedef struct poisson_request {
 
 typedef struct poisson_req_times {
     double submit_ms, admit_ms, done_ms; /* on the server's steady clock, from server start */
+    int64_t n_unknowns;                  /* length of the solution once finished (N + n_mghost), else 0 */
 } poisson_req_times;
 
 int32_t poisson_server_create(const poisson_server_opts *opts, poisson_server **out);
@@ -248,7 +255,9 @@ int32_t poisson_submit(poisson_server *srv, const poisson_request *req, uint64_t
 /* Non-blocking: IBM_EAGAIN while queued or running; on completion copies the
  * solution (host double[N + n_mghost], may be NULL) and stats, frees the
  * request and returns its solve status.  *state (may be NULL) gets IBM_REQ_*.
- * x_len is the capacity of x_out in doubles. */
+ * x_len is the capacity of x_out in doubles: when it is too small the call
+ * returns IBM_EINVAL, keeps the request and reports the needed length in
+ * times->n_unknowns. */
 int32_t poisson_poll(poisson_server *srv, uint64_t ticket, double *x_out, int64_t x_len, poisson_stats *stats,
                      poisson_req_times *times, int32_t *state);
 /* Block until every submitted request has finished. */

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libibmpoisson.so")
 IBM_OK, IBM_EINVAL, IBM_EGEOM, IBM_ENOMEM, IBM_EHIP, IBM_ENOCONV, IBM_EBREAKDOWN, IBM_EAGAIN, IBM_ENOTFOUND = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC_FP64, PREC_MIXED = 0, 1
+IBM_REQ_QUEUED, IBM_REQ_RUNNING, IBM_REQ_DONE, IBM_REQ_FAILED = 0, 1, 2, 3
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -72,7 +73,8 @@ class _Request(ctypes.Structure):
 
 
 class ReqTimes(ctypes.Structure):
-    _fields_ = [("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
+    _fields_ = [("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
+                ("n_unknowns", ctypes.c_int64)]
 
 
 EXPORTS = ["ibm_classify", "ibm_build_ghost_stencils", "ibm_stencils_info", "ibm_stencils_export",
@@ -290,6 +292,8 @@ class Solver:
 
 
 def workspace_estimate(nx, ny, nz, n_rows, precision=PREC_FP64) -> int:
+    if isinstance(precision, str):
+        precision = PREC_MIXED if precision == "mixed" else PREC_FP64
     b = ctypes.c_size_t()
     _check(lib().poisson_workspace_estimate(nx, ny, nz, ctypes.c_int64(n_rows), precision, ctypes.byref(b)),
            "poisson_workspace_estimate")
@@ -310,6 +314,7 @@ class Server:
 
     def __init__(self, hbm_budget: int, max_slots: int = 16, device: int = 0):
         self.h = ctypes.c_void_p()
+        self._cells = {}
         o = _ServerOpts(hbm_budget, max_slots, device)
         _check(lib().poisson_server_create(ctypes.byref(o), ctypes.byref(self.h)), "poisson_server_create")
 
@@ -321,17 +326,26 @@ class Server:
                        opts if opts is not None else default_opts(**kw))
         t = ctypes.c_uint64()
         _check(lib().poisson_submit(self.h, ctypes.byref(req), ctypes.byref(t)), "poisson_submit")
+        self._cells[t.value] = (len(xf) - 1) * (len(yf) - 1) * (len(zf) - 1)
         return t.value
 
-    def poll(self, ticket: int, n_unknowns: int = 0):
-        """(rc, state, x or None, stats, times); rc IBM_EAGAIN while unfinished."""
-        x = np.zeros(max(n_unknowns, 1))
-        st = PoissonStats()
-        tm = ReqTimes()
-        state = ctypes.c_int32()
-        rc = lib().poisson_poll(self.h, ctypes.c_uint64(ticket), _dptr(x) if n_unknowns else None,
-                                ctypes.c_int64(n_unknowns), ctypes.byref(st), ctypes.byref(tm), ctypes.byref(state))
-        return rc, state.value, (x if n_unknowns else None), st, tm
+    def poll(self, ticket: int, want_x: bool = True):
+        """(rc, state, x or None, stats, times); rc IBM_EAGAIN while unfinished.
+        A finished request is consumed by the call that returns it."""
+        n = self._cells.get(ticket, 0) if want_x else 0
+        while True:
+            x = np.zeros(max(n, 1))
+            st = PoissonStats()
+            tm = ReqTimes()
+            state = ctypes.c_int32()
+            rc = lib().poisson_poll(self.h, ctypes.c_uint64(ticket), _dptr(x) if n else None, ctypes.c_int64(n),
+                                    ctypes.byref(st), ctypes.byref(tm), ctypes.byref(state))
+            if rc == IBM_EINVAL and n and tm.n_unknowns > n:
+                n = tm.n_unknowns  # membrane ghost unknowns follow the cells
+                continue
+            if rc != IBM_EAGAIN:
+                self._cells.pop(ticket, None)
+            return rc, state.value, (x[:tm.n_unknowns] if n else None), st, tm
 
     def drain(self):
         _check(lib().poisson_server_drain(self.h), "poisson_server_drain")

@@ -225,6 +225,7 @@ extern "C" int32_t poisson_poll(poisson_server *S, uint64_t ticket, double *x_ou
         if (state) *state = r->state;
         if (times) *times = r->times;
         if (r->state == IBM_REQ_QUEUED || r->state == IBM_REQ_RUNNING) { rc = IBM_EAGAIN; return; }
+        if (times) times->n_unknowns = (int64_t)r->x.size();
         if (stats) *stats = r->stats;
         if (x_out && !r->x.empty()) {
             IBM_REQUIRE(x_len >= (int64_t)r->x.size(), IBM_EINVAL, "x_out too short");

@@ -1,0 +1,141 @@
+"""Serving loop through the C ABI (needs an MI355X).
+
+Every request solved in the mix must equal the same request solved alone
+(the solve is deterministic, so the target is bitwise; the hard bound is the
+1e-8 tolerance), admission must follow the memory budget and the slot limit,
+and requests that arrive while others run must overlap with them.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2605_04335_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_04335_amd as P
+    return P
+
+
+def requests(n, seed, emin=32, emax=64):
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n):
+        p = W.serving_request(rng, emin, emax)
+        p.f = W.noise_rhs(p.npts, 1000 + seed * 100 + q)
+        out.append(p)
+    return out
+
+
+def solve_alone(P, p, **opts):
+    import torch
+    flags, _ = P.classify(p.xf, p.yf, p.zf, p.bodies)
+    st = P.build_ghost_stencils(p.xf, p.yf, p.zf, p.bodies, flags)
+    sol = P.Solver(p.xf, p.yf, p.zf, flags, st, **opts)
+    x, stats = sol.solve(torch.from_numpy(p.f).cuda())
+    return x.cpu().numpy(), stats
+
+
+def wait_all(P, srv, tickets, timeout_s=120):
+    res = {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        assert time.time() - t0 < timeout_s, "serving timed out"
+        for t in tickets:
+            if t in res:
+                continue
+            rc, state, x, st, tm = srv.poll(t)
+            if rc != P.IBM_EAGAIN:
+                res[t] = (rc, state, x, st, (tm.submit_ms, tm.admit_ms, tm.done_ms))
+        time.sleep(0.002)
+    return res
+
+
+def test_mix_equals_alone(P):
+    reqs = requests(5, 11)
+    reqs.append(W.membrane_case(64, nc=40, ns=120))
+    opts = dict(precision="mixed", tol=1e-8, max_iter=60)
+    alone = []
+    for q, p in enumerate(reqs):
+        say("alone", q, p.shape, len(p.bodies))
+        alone.append(solve_alone(P, p, **opts))
+    srv = P.Server(hbm_budget=16 << 30, max_slots=3)
+    try:
+        tickets = [srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, **opts) for p in reqs]
+        res = wait_all(P, srv, tickets)
+    finally:
+        srv.close()
+    identical = 0
+    for q, t in enumerate(tickets):
+        rc, state, x, st, times = res[t]
+        xa, sa = alone[q]
+        assert rc == P.IBM_OK and state == P.IBM_REQ_DONE
+        assert st.rel_residual <= 1e-8
+        assert x.shape == xa.shape
+        d = float(np.linalg.norm(x - xa) / np.linalg.norm(xa))
+        say("request", q, "rel diff %.3e" % d, "iterations", st.iterations, sa.iterations)
+        assert d <= 1e-8
+        identical += int(np.array_equal(x, xa))
+    say("bitwise identical:", identical, "of", len(tickets))
+    assert identical == len(tickets)
+    # with 3 slots, some requests ran at the same time
+    iv = sorted(r[4][1:] for r in res.values())
+    assert any(iv[q + 1][0] < iv[q][1] for q in range(len(iv) - 1))
+
+
+def test_slot_limit_serialises(P):
+    reqs = requests(3, 12)
+    srv = P.Server(hbm_budget=16 << 30, max_slots=1)
+    try:
+        tickets = [srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, precision="mixed", tol=1e-8) for p in reqs]
+        res = wait_all(P, srv, tickets)
+    finally:
+        srv.close()
+    iv = sorted(r[4][1:] for r in res.values())
+    for q in range(len(iv) - 1):
+        assert iv[q + 1][0] >= iv[q][1]
+    assert all(r[0] == P.IBM_OK for r in res.values())
+
+
+def test_admission_by_footprint(P):
+    p = requests(1, 13)[0]
+    bytes_needed = P.workspace_estimate(*p.shape, 0, "mixed")
+    srv = P.Server(hbm_budget=max(1, bytes_needed // 4), max_slots=4)
+    try:
+        t = srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, precision="mixed", tol=1e-8)
+        res = wait_all(P, srv, [t])
+        rc, state = res[t][0], res[t][1]
+        assert rc == P.IBM_ENOMEM and state == P.IBM_REQ_FAILED
+        rc, *_ = srv.poll(t)
+        assert rc == P.IBM_ENOTFOUND
+    finally:
+        srv.close()
+
+
+def test_poll_states(P):
+    p = W.sphere_ellipsoid_case(96)
+    srv = P.Server(hbm_budget=16 << 30, max_slots=2)
+    try:
+        t = srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, precision="mixed", tol=1e-8)
+        rc, state, x, st, tm = srv.poll(t)
+        assert rc in (P.IBM_EAGAIN, P.IBM_OK)
+        if rc == P.IBM_EAGAIN:
+            assert state in (P.IBM_REQ_QUEUED, P.IBM_REQ_RUNNING)
+            res = wait_all(P, srv, [t])
+            assert res[t][0] == P.IBM_OK
+        rc, *_ = srv.poll(123456789)
+        assert rc == P.IBM_ENOTFOUND
+        srv.drain()
+    finally:
+        srv.close()
