@@ -44,6 +44,14 @@ __device__ __forceinline__ void st<bf16>(bf16 *a, long long i, double v) { a[i] 
 template <>
 __device__ __forceinline__ double ld<bf16>(const bf16 *a, long long i) { return (double)(float)a[i]; }
 
+// load at a block-uniform base plus a 32-bit element offset (the compiler
+// then addresses with a scalar base and one 32-bit VGPR per load)
+template <class T>
+__device__ __forceinline__ T ldu(const T *base, uint32_t i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
+}
+
 // v rounded to the precision of storage type T
 template <class T>
 __device__ __forceinline__ double round_to(double v) { return (double)(T)v; }
@@ -787,36 +795,46 @@ __global__ void __launch_bounds__(TPB) k0_restrict_res(Lv F, Lv C, Geo Gc, long 
     int I, J, k0, k1;
     if (geo_tile(Gc, I, J, k0, k1)) {
         const long long Nh = F.Nh, H = F.H, pl = H * F.ny;
-        const double snk = sink ? sink[0] : 0.0;
+        typedef T R;  // arithmetic in the precision of the level-0 vectors
+        const R snk = sink ? (R)sink[0] : (R)0;
         // x: coefficients of the two cells i = 2I + dx; the outer neighbour of
         // i = 2I is half I-1, of i = 2I+1 half I+1 (clamped, zero coefficient)
-        double cpx[2], cmx[2], wx[2];
+        R cpx[2], cmx[2], wx[2];
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx) {
             const int i = 2 * I + dx;
-            cpx[dx] = i + 1 < F.nx ? F.cp[0][i] : 0.0;
-            cmx[dx] = i > 0 ? F.cm[0][i] : 0.0;
-            wx[dx] = F.w[0][i];
+            cpx[dx] = i + 1 < F.nx ? (R)F.cp[0][i] : (R)0;
+            cmx[dx] = i > 0 ? (R)F.cm[0][i] : (R)0;
+            wx[dx] = (R)F.w[0][i];
         }
         const int hm = I > 0 ? I - 1 : I, hp = 2 * I + 2 < F.nx ? I + 1 : I;
-        double cpy[2], cmy[2], wy[2];
+        R cpy[2], cmy[2], wy[2];
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
             const int j = 2 * J + dy;
-            cpy[dy] = j + 1 < F.ny ? F.cp[1][j] : 0.0;
-            cmy[dy] = j > 0 ? F.cm[1][j] : 0.0;
-            wy[dy] = F.w[1][j];
+            cpy[dy] = j + 1 < F.ny ? (R)F.cp[1][j] : (R)0;
+            cmy[dy] = j > 0 ? (R)F.cm[1][j] : (R)0;
+            wy[dy] = (R)F.w[1][j];
         }
-        const long long rowm = H * max(2 * J - 1, 0), row0 = H * (2 * J), row1 = H * (2 * J + 1),
-                        rowp = H * min(2 * J + 2, F.ny - 1);
+        // every load of this thread is within fine planes [kb, 2 k1]: block-uniform
+        // per-colour bases and 32-bit offsets from them
+        const int kb = max(2 * k0 - 1, 0);
+        const T *xb[2] = {x + pl * kb, x + Nh + pl * kb};
+        const T *bb[2] = {b + pl * kb, b + Nh + pl * kb};
+        const T *rb[2] = {rsp + pl * kb, rsp + Nh + pl * kb};
+        const uint8_t *fb[2] = {F.f + pl * kb, F.f + Nh + pl * kb};
+        const uint32_t rowm = (uint32_t)(H * max(2 * J - 1, 0)), row0 = (uint32_t)(H * (2 * J)),
+                       row1 = (uint32_t)(H * (2 * J + 1)), rowp = (uint32_t)(H * min(2 * J + 2, F.ny - 1));
+        const uint32_t pl32 = (uint32_t)pl;
+        auto zoff = [&](int kk) { return pl32 * (uint32_t)(min(max(kk, 0), F.nz - 1) - kb); };
         // v[c][dy][q]: colour c, row 2J+dy, plane 2K-1+q
         T v[2][2][4];
         auto ldcol = [&](int kk, int q) {
-            const long long z = pl * min(max(kk, 0), F.nz - 1);
+            const uint32_t z = zoff(kk);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                v[c][0][q] = x[c * Nh + I + row0 + z];
-                v[c][1][q] = x[c * Nh + I + row1 + z];
+                v[c][0][q] = ldu(xb[c], I + row0 + z);
+                v[c][1][q] = ldu(xb[c], I + row1 + z);
             }
         };
         ldcol(2 * k0 - 1, 0);
@@ -832,14 +850,14 @@ __global__ void __launch_bounds__(TPB) k0_restrict_res(Lv F, Lv C, Geo Gc, long 
             for (int q = 0; q < 8; ++q) {
                 const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
                 const int c = (dx + dy + dz) & 1, o = 1 - c;
-                const long long zk = pl * (2 * K + dz);
-                const long long s = c * Nh + I + (dy ? row1 : row0) + zk;
-                fq[q] = F.f[s];
-                bq[q] = b[s];
-                xq[q] = x[o * Nh + (dx ? hp : hm) + (dy ? row1 : row0) + zk];
-                yq[q] = x[o * Nh + I + (dy ? rowp : rowm) + zk];
+                const uint32_t zk = zoff(2 * K + dz);
+                const uint32_t s = I + (dy ? row1 : row0) + zk;
+                fq[q] = ldu(fb[c], s);
+                bq[q] = ldu(bb[c], s);
+                xq[q] = ldu(xb[o], (dx ? hp : hm) + (dy ? row1 : row0) + zk);
+                yq[q] = ldu(xb[o], I + (dy ? rowp : rowm) + zk);
             }
-            double sv = 0.0, svr = 0.0;
+            R sv = 0, svr = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
@@ -847,31 +865,32 @@ __global__ void __launch_bounds__(TPB) k0_restrict_res(Lv F, Lv C, Geo Gc, long 
                 const int k = 2 * K + dz;
                 const uint8_t f = fq[q];
                 if (!active0(f)) continue;
-                double r;
+                R r;
+                const uint32_t s = I + (dy ? row1 : row0) + zoff(k);
                 if (f & (F_GHOST | F_MGHOST)) {
-                    r = ld(rsp, c * Nh + I + (dy ? row1 : row0) + pl * k);
+                    r = ldu(rb[c], s);
                 } else {
-                    const double xv = v[c][dy][1 + dz];
-                    const double xin = v[o][dy][1 + dz];
-                    const double xout = xq[q];
-                    const double xpx = dx ? xout : xin, xmx = dx ? xin : xout;
-                    const double xpy = dy ? (double)yq[q] : (double)v[o][1][1 + dz];
-                    const double xmy = dy ? (double)v[o][0][1 + dz] : (double)yq[q];
-                    const double xpz = v[o][dy][2 + dz], xmz = v[o][dy][dz];
-                    const double czp = F.cp[2][k], czm = F.cm[2][k];  // zero at the walls
-                    const double dg = cpx[dx] + cmx[dx] + cpy[dy] + cmy[dy] + czp + czm;
-                    const double n = cpx[dx] * xpx + cmx[dx] * xmx + cpy[dy] * xpy + cmy[dy] * xmy + czp * xpz +
-                                     czm * xmz;
-                    double bv = bq[q];
-                    if (c * Nh + I + (dy ? row1 : row0) + pl * k == pin) bv -= snk;
+                    const R xv = v[c][dy][1 + dz];
+                    const R xin = v[o][dy][1 + dz];
+                    const R xout = xq[q];
+                    const R xpx = dx ? xout : xin, xmx = dx ? xin : xout;
+                    const R xpy = dy ? yq[q] : v[o][1][1 + dz];
+                    const R xmy = dy ? v[o][0][1 + dz] : yq[q];
+                    const R xpz = v[o][dy][2 + dz], xmz = v[o][dy][dz];
+                    const R czp = (R)F.cp[2][k], czm = (R)F.cm[2][k];  // zero at the walls
+                    const R dg = cpx[dx] + cmx[dx] + cpy[dy] + cmy[dy] + czp + czm;
+                    const R n = cpx[dx] * xpx + cmx[dx] * xmx + cpy[dy] * xpy + cmy[dy] * xmy + czp * xpz +
+                                czm * xmz;
+                    R bv = bq[q];
+                    if (c * Nh + pl * kb + s == pin) bv -= snk;
                     r = bv - (n - dg * xv);
                 }
-                const double V = wx[dx] * wy[dy] * F.w[2][k];
+                const R V = wx[dx] * wy[dy] * (R)F.w[2][k];
                 sv += V;
                 svr += V * r;
             }
             const long long sc = slot(C, (I + J + K) & 1, I >> 1, J, K);
-            st(bc, sc, sv > 0.0 ? svr / sv : 0.0);
+            st(bc, sc, sv > 0 ? (double)(svr / sv) : 0.0);
             if (C.f[sc] & 1) a.v[0] += C.w[0][I] * C.w[1][J] * C.w[2][K] * ld(bc, sc);
 #pragma unroll
             for (int c = 0; c < 2; ++c)
@@ -1422,10 +1441,10 @@ __global__ void __launch_bounds__(TPB) k_copy_norm(Walk W, const TA *a, TB *b, T
 }
 
 template <class T>
-__global__ void __launch_bounds__(TPB) k_add(Walk W, double *x, const T *d)
+__global__ void __launch_bounds__(TPB) k_add(Walk W, double *x, const T *d, double a = 1.0)
 {
     WALK_BEGIN(W, p)
-        x[p] += ld(d, p);
+        x[p] += a * ld(d, p);
     WALK_END
 }
 

@@ -109,7 +109,8 @@ struct poisson_ctx {
     long long N = 0, nm = 0, ng = 0, nrows = 0, n_fallback = 0, pin = 0;
     long long N2 = 0, Nt = 0;  // 2 Nh cell slots, + membrane unknowns
     double vol_fluid = 0.0, vol_pin = 0.0;
-    int tail0 = 1;             // first level of the single-workgroup tail
+    int tail0 = 1;             // first level of the single-workgroup tail (FP32 levels in the mixed form)
+    int tail0d = 1;            // the same for FP64 levels
     DBuf<int32_t> rslot, rcol, mslot, mcol, mcolor;
     DBuf<double> rw, rsG, rdlb;
     std::vector<Level> lv;
@@ -118,7 +119,12 @@ struct poisson_ctx {
     Walk W4;   // over ceil(Nt / 4) groups of 4 unknowns
     Walk Wc;   // over 2 Nh cell slots
     DBuf<double> x, r, rh, p, v, ph, sh, t, rsp, b;
-    DBuf<float> fd, fr, frh, fp, fv, fph, fsh, ft, frsp;
+    DBuf<float> fr, frh, fp, fv, fph, fsh, ft, frsp;
+    // mixed: the inner solution accumulates in FP64 (a smooth correction
+    // rounded to FP32 loses its small Laplacian: the operator multiplies the
+    // rounding by up to |A| ~ 12/h^2)
+    DBuf<double> d64;
+    DBuf<double> r2;           // mixed: right-hand side of the FP64 fallback solve
     DBuf<double> gtmp, sc, part;
     double *hsc = nullptr;
     hipStream_t cs = nullptr;
@@ -258,7 +264,7 @@ void fine_smooth(poisson_ctx &c, T *x, const T *b, const double *sink, bool from
     for (int color = 0; color < 2; ++color) {
         if (from_zero && color == 0) {
             // the other colour is zeroed too: ghost rows and membrane rows read it before its sweep
-            const long long pin_s = c.pin < L.Nh ? c.pin : -1;
+            const long long pin_s = (sink && c.pin < L.Nh) ? c.pin : -1;
             k0_sweep_zero<T><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, pin_s, x, x + L.Nh, b, L.lv.f, sink, 0);
             if (c.nm) {
                 Walk Wt = make_walk(c.nm);
@@ -268,7 +274,7 @@ void fine_smooth(poisson_ctx &c, T *x, const T *b, const double *sink, bool from
             // (from zero, the black slots were zeroed by the red sweep; ghost
             // values set since then must survive, so this is an ordinary sweep)
             const long long co = (long long)color * L.Nh;
-            const long long pin_s = (c.pin >= co && c.pin < co + L.Nh) ? c.pin - co : -1;
+            const long long pin_s = (sink && c.pin >= co && c.pin < co + L.Nh) ? c.pin - co : -1;
             if (!from_zero) prof_begin(c, PK_SWEEP0, s);
             k0_sweep<T><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, pin_s, x + co, x + (L.Nh - co), b + co, L.lv.f + co,
                                                  sink, color);
@@ -323,7 +329,7 @@ void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
                                                          Store<T>::b(L1), c.part.p);
         IBM_LAUNCH_CHECK();
         fin(c, L1.geon.nb, FIN_MEAN, S_MEAN0 + 1, L1.volA, s);
-        const int lt = c.tail0;
+        const int lt = std::is_same<T, double>::value ? c.tail0d : c.tail0;
         for (int l = 1; l < lt; ++l) {
             Level &L = c.lv[l];
             const double *mean = c.sc.p + S_MEAN0 + l;
@@ -381,8 +387,8 @@ void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
 
 // One BiCGSTAB iteration (van der Vorst 1992, right preconditioning): all
 // scalars stay on the device.
-template <class T>
-void bicg_iteration(poisson_ctx &c, T *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, hipStream_t s)
+template <class T, class TX>
+void bicg_iteration(poisson_ctx &c, TX *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, hipStream_t s)
 {
     const Walk &W = c.W4;
     const Lv &L = c.L0();
@@ -399,7 +405,7 @@ void bicg_iteration(poisson_ctx &c, T *y, T *r, T *rh, T *p, T *v, T *ph, T *sh,
     np = launch_apply<T>(c, M_PINZERO, false, 2, sh, t, nullptr, nullptr, r, nullptr, s);
     fin(c, np, FIN_OMEGA, 0, 0.0, s);
     prof_begin(c, PK_XR, s);
-    k_xr_update4<T, T><<<W.nb, TPB, 0, s>>>(L, W, c.Nt, c.pin, y, ph, sh, r, t, rh, c.sc.p, c.part.p,
+    k_xr_update4<T, TX><<<W.nb, TPB, 0, s>>>(L, W, c.Nt, c.pin, y, ph, sh, r, t, rh, c.sc.p, c.part.p,
                                               PSTRIDE);
     prof_end(c, PK_XR, s);
     IBM_LAUNCH_CHECK();
@@ -415,12 +421,12 @@ void read_scalars(poisson_ctx &c, hipStream_t s)
 
 // Right-preconditioned BiCGSTAB on A y = rhs; y starts at zero.  Returns the
 // iteration count; *rc gets the status.
-template <class T>
-int bicgstab(poisson_ctx &c, const T *rhs, T *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, double tol, int maxit,
+template <class T, class TX>
+int bicgstab(poisson_ctx &c, const T *rhs, TX *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, double tol, int maxit,
              bool true_check, hipGraphExec_t *graph, hipStream_t s, int *rc, double *relout)
 {
     const Walk &W = c.W0;
-    k_fill<T><<<W.nb, TPB, 0, s>>>(W, y, 0.0);
+    k_fill<TX><<<W.nb, TPB, 0, s>>>(W, y, 0.0);
     k_fill<T><<<W.nb, TPB, 0, s>>>(W, p, 0.0);
     k_fill<T><<<W.nb, TPB, 0, s>>>(W, v, 0.0);
     k_copy_norm<T, T><<<W.nb, TPB, 0, s>>>(W, rhs, r, rh, c.part.p);
@@ -438,7 +444,7 @@ int bicgstab(poisson_ctx &c, const T *rhs, T *y, T *r, T *rh, T *p, T *v, T *ph,
         hipGraph_t gr;
         c.capturing = true;
         IBM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        bicg_iteration<T>(c, y, r, rh, p, v, ph, sh, t, s);
+        bicg_iteration<T, TX>(c, y, r, rh, p, v, ph, sh, t, s);
         IBM_HIP(hipStreamEndCapture(s, &gr));
         c.capturing = false;
         IBM_HIP(hipGraphInstantiate(graph, gr, nullptr, nullptr, 0));
@@ -449,16 +455,18 @@ int bicgstab(poisson_ctx &c, const T *rhs, T *y, T *r, T *rh, T *p, T *v, T *ph,
     while (it < maxit) {
         ++it;
         if (use_graph) IBM_HIP(hipGraphLaunch(*graph, s));
-        else bicg_iteration<T>(c, y, r, rh, p, v, ph, sh, t, s);
+        else bicg_iteration<T, TX>(c, y, r, rh, p, v, ph, sh, t, s);
         read_scalars(c, s);
         const double st = c.hsc[S_STATUS];
         rel = c.hsc[S_REL];
         if (log_level() >= 2)
-            fprintf(stderr, "[ibm]   it %d rel %.3e status %g\n", it, rel, st);
+            fprintf(stderr, "[ibm]   it %d rel %.3e status %g alpha %.3e omega %.3e sinks %.3e %.3e\n", it, rel, st,
+                    c.hsc[S_ALPHA], c.hsc[S_OMEGA], c.hsc[S_SINKP], c.hsc[S_SINKS]);
         if (st >= 2.0 || !std::isfinite(rel)) { *rc = IBM_EBREAKDOWN; break; }
         if (rel <= tol) {
+            if constexpr (!std::is_same<T, TX>::value) { *rc = IBM_OK; break; }  // inner solves: no true check
             if (!true_check) { *rc = IBM_OK; break; }
-            int np = launch_apply<T>(c, M_PINNED, true, 2, y, t, rhs, nullptr, rh, nullptr, s);
+            int np = launch_apply<T>(c, M_PINNED, true, 2, (const T *)y, t, rhs, nullptr, rh, nullptr, s);
             k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
             read_scalars(c, s);
             double trel = std::sqrt(c.hsc[S_TMP] / c.hsc[S_BN2]);
@@ -541,7 +549,7 @@ size_t estimate_bytes(int nx, int ny, int nz, long long nrows, int precision)
     size_t b = (size_t)2 * Nh;  // flags
     b += (size_t)nrows * (8 * 4 + 8 * 8 + 16 + 8 + 4 + 6 * 4 + 4);
     b += (size_t)Nt * 8 * (precision == IBM_PREC_MIXED ? 4 : 10);
-    if (precision == IBM_PREC_MIXED) b += (size_t)Nt * 4 * 9;
+    if (precision == IBM_PREC_MIXED) b += (size_t)Nt * (4 * 8 + 8);
     long long Nc = 2 * Nh;
     size_t coarse = 0;
     while (true) {
@@ -768,18 +776,20 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
         }
     }
     // device views, coarse storage, tail start
-    c->tail0 = nl;
-    {
-        const size_t tsz = c->mixed ? sizeof(float) : sizeof(double);
+    for (int pass = 0; pass < 2; ++pass) {
+        const size_t tsz = pass ? sizeof(double) : sizeof(float);
+        int &t0 = pass ? c->tail0d : c->tail0;
+        t0 = nl;
         int off = 0;
         for (int l = nl - 1; l >= 1 && (nl - l) <= 8; --l) {
             int m, xo, bo, o2 = off;
             tail_layout(c->lv[l].Nh, tsz, o2, m, xo, bo);
             if (o2 > TAIL_LDS) break;
             off = o2;
-            c->tail0 = l;
+            t0 = l;
         }
     }
+    if (!c->mixed) c->tail0 = c->tail0d;
     for (int l = 0; l < nl; ++l) {
         Level &L = c->lv[l];
         Lv &v = L.lv;
@@ -810,7 +820,7 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
     if (!c->mixed) {
         c->rh.alloc(Nt); c->p.alloc(Nt); c->v.alloc(Nt); c->ph.alloc(Nt); c->sh.alloc(Nt); c->rsp.alloc(Nt);
     } else {
-        c->fd.alloc(Nt); c->fr.alloc(Nt); c->frh.alloc(Nt); c->fp.alloc(Nt); c->fv.alloc(Nt);
+        c->d64.alloc(Nt); c->fr.alloc(Nt); c->frh.alloc(Nt); c->fp.alloc(Nt); c->fv.alloc(Nt);
         c->fph.alloc(Nt); c->fsh.alloc(Nt); c->ft.alloc(Nt); c->frsp.alloc(Nt);
     }
     c->gtmp.alloc(std::max<long long>(R, 1));
@@ -869,13 +879,27 @@ void assemble_rhs(poisson_ctx &c, const double *f, const double *gval, double *b
 }
 
 // solve A x = b (assembled, in c.b, split) into c.x; returns status
+// FP64 storage of a mixed context, allocated on first need: the coarse FP64
+// levels and the FP64 Krylov vectors (the FP64 cycle uses its own tail start)
+void ensure_fp64(poisson_ctx &c)
+{
+    for (size_t l = 1; l < c.lv.size(); ++l) {
+        Level &L = c.lv[l];
+        if (!L.x64.p) L.x64.alloc(2 * L.Nh);
+        if (!L.b64.p) L.b64.alloc(2 * L.Nh);
+    }
+    DBuf<double> *v[] = {&c.rh, &c.p, &c.v, &c.ph, &c.sh, &c.rsp, &c.r2};
+    for (DBuf<double> *b : v)
+        if (!b->p) b->alloc(c.Nt);
+}
+
 int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
 {
     const poisson_opts &o = c.opts;
     int rc = IBM_ENOCONV, its = 0, outer = 0;
     double rel = 1.0;
     if (!c.mixed) {
-        its = bicgstab<double>(c, c.b.p, c.x.p, c.r.p, c.rh.p, c.p.p, c.v.p, c.ph.p, c.sh.p, c.t.p, o.tol, o.max_iter,
+        its = bicgstab<double, double>(c, c.b.p, c.x.p, c.r.p, c.rh.p, c.p.p, c.v.p, c.ph.p, c.sh.p, c.t.p, o.tol, o.max_iter,
                                true, &c.g64, s, &rc, &rel);
         if (log_enabled()) fprintf(stderr, "[ibm] fp64: %d iterations to %.3e (rc %d)\n", its, rel, rc);
     } else {
@@ -887,6 +911,7 @@ int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
         IBM_LAUNCH_CHECK();
         read_scalars(c, s);
         const double bn2 = c.hsc[S_TMP2];
+        double prev = HUGE_VAL;
         for (outer = 0; outer <= o.max_outer; ++outer) {
             if (bn2 == 0.0) { rc = IBM_OK; rel = 0.0; break; }
             // r64 = b - A x (pinned) and its norm
@@ -897,7 +922,35 @@ int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
             rel = std::sqrt(c.hsc[S_TMP] / bn2);
             if (!std::isfinite(rel)) { rc = IBM_EBREAKDOWN; break; }
             if (rel <= o.tol) { rc = IBM_OK; break; }
+            if (rel > prev) {
+                // the FP32 correction made the FP64 residual larger: refinement
+                // has stalled (the FP32 solves cannot resolve this system: the
+                // condition number times the FP32 unit roundoff is not small).
+                // Undo the last correction and finish with an FP64 BiCGSTAB on
+                // the remaining residual.
+                k_add<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.d64.p, -1.0);
+                IBM_LAUNCH_CHECK();
+                if (log_enabled())
+                    fprintf(stderr, "[ibm] outer %d: rel %.3e > %.3e, refinement stalled: FP64 fallback\n", outer, rel,
+                            prev);
+                ensure_fp64(c);
+                launch_apply<double>(c, M_PINNED, true, 2, c.x.p, c.r2.p, c.b.p, nullptr, c.b.p, nullptr, s);
+                int frc;
+                double frel;
+                its += bicgstab<double, double>(c, c.r2.p, c.d64.p, c.r.p, c.rh.p, c.p.p, c.v.p, c.ph.p, c.sh.p,
+                                                c.t.p, o.tol / prev, o.max_iter, true, &c.g64, s, &frc, &frel);
+                k_add<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.d64.p);
+                int np = launch_apply<double>(c, M_PINNED, true, 2, c.x.p, c.r.p, c.b.p, nullptr, c.b.p, nullptr, s);
+                k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
+                IBM_LAUNCH_CHECK();
+                read_scalars(c, s);
+                rel = std::sqrt(c.hsc[S_TMP] / bn2);
+                rc = frc == IBM_EBREAKDOWN ? frc : (rel <= o.tol ? IBM_OK : IBM_ENOCONV);
+                if (log_enabled()) fprintf(stderr, "[ibm] fp64 fallback: rel %.3e (rc %d)\n", rel, rc);
+                break;
+            }
             if (outer == o.max_outer) { rc = IBM_ENOCONV; break; }
+            prev = rel;
             // inner FP32 solve of A d = r64 (the inner residual vector starts as r64);
             // it asks only for the reduction still needed, never less than inner_tol
             k_copy<double, float><<<W.nb, TPB, 0, s>>>(W, c.r.p, c.fr.p);
@@ -905,14 +958,14 @@ int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
             int irc;
             double irel;
             const double itol = std::max(o.inner_tol, 0.5 * o.tol / rel);
-            const int n_in = bicgstab<float>(c, c.fr.p, c.fd.p, c.fr.p, c.frh.p, c.fp.p, c.fv.p, c.fph.p, c.fsh.p,
+            const int n_in = bicgstab<float, double>(c, c.fr.p, c.d64.p, c.fr.p, c.frh.p, c.fp.p, c.fv.p, c.fph.p, c.fsh.p,
                                              c.ft.p, itol, o.max_iter, false, &c.g32, s, &irc, &irel);
             its += n_in;
             if (log_enabled())
                 fprintf(stderr, "[ibm] outer %d: rel %.3e, inner tol %.1e: %d iterations to %.2e (rc %d)\n", outer, rel,
                         itol, n_in, irel, irc);
             if (irc == IBM_EBREAKDOWN) { rc = irc; break; }
-            k_add<float><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.fd.p);
+            k_add<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.d64.p);
             IBM_LAUNCH_CHECK();
         }
     }

@@ -1,0 +1,116 @@
+"""Full-size checks on the 512^3 membrane configuration the benchmark times
+(needs an MI355X).
+
+At this size the oracle still classifies, builds the ghost rows, applies the
+operator and runs one V-cycle in seconds, so those are compared element by
+element; the solves are checked by properties that hold at any size: the
+oracle's own operator applied to the GPU solution of a manufactured system
+(b = A x_true) leaves a residual within the tolerance, the error stays within
+kappa * tol, and the mixed and FP64 solutions agree.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_04335_amd import workloads as W
+from tests import refpy
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_04335_amd as P
+    p = W.membrane_case(512)
+    say("c3 oracle classification + ghost rows")
+    O = oracle.setup(p.xf, p.yf, p.zf, p.bodies)
+    flags, cst = P.classify(p.xf, p.yf, p.zf, p.bodies)
+    st = P.build_ghost_stencils(p.xf, p.yf, p.zf, p.bodies, flags)
+    return P, p, O, flags, st
+
+
+def test_c3_classification_and_ghost_rows(c3):
+    P, p, O, flags, st = c3
+    say("c3 flags")
+    g = flags.cpu().numpy()
+    assert np.array_equal(g, O.flags), "mismatching cells: %d" % int(np.sum(g != O.flags))
+    e = st.export()
+    assert e["ng"] == O.st.ng and e["nm"] == O.st.nm
+    assert np.array_equal(e["cell"], O.st.row_cell)
+    assert np.array_equal(e["col"], O.st.col)
+    assert np.array_equal(e["rfl"], O.st.rfl)
+    assert np.abs(e["w"] - O.st.w).max(initial=0) < 1e-13
+    assert np.allclose(e["sG"], O.st.sG, rtol=1e-14, atol=0)
+    assert np.abs(e["dlb"] - O.st.dlb).max(initial=0) < 1e-13
+
+
+def test_c3_operator_and_vcycle(c3):
+    import torch
+    P, p, O, flags, st = c3
+    sol = P.Solver(p.xf, p.yf, p.zf, flags, st, precision="fp64")
+    n = sol.n_unknowns
+    x = np.random.default_rng(31).uniform(-1, 1, n)
+    x[~refpy.active_mask(O.flags, O.st.nm)] = 0.0
+    say("c3 operator")
+    y = sol.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert rel(y, oracle.apply(p.xf, p.yf, p.zf, O.flags, O.st, x)) < 1e-14
+    say("c3 rhs")
+    b = sol.assemble_rhs(torch.from_numpy(p.f).cuda()).cpu().numpy()
+    bo = oracle.assemble_rhs(p.xf, p.yf, p.zf, O.flags, O.st, p.f)
+    assert rel(b, bo) < 1e-14
+    say("c3 V-cycle")
+    z = sol.precond(torch.from_numpy(bo).cuda()).cpu().numpy()
+    # one linear map, but its global sums (the pin sink over 1.3e8 terms with
+    # heavy cancellation, divided by the pin volume ~1e-9, and one mean per
+    # coarse level) are reduced in a different order than the oracle's:
+    # measured 6.9e-11 here (1.5e-12 at 64^3)
+    assert rel(z, oracle.vcycle(p.xf, p.yf, p.zf, O.flags, O.st, bo)) < 1e-9
+
+
+def test_c3_manufactured_mixed_and_fp64(c3):
+    import torch
+    P, p, O, flags, st = c3
+    s64 = P.Solver(p.xf, p.yf, p.zf, flags, st, precision="fp64", tol=1e-12, max_iter=200)
+    n = s64.n_unknowns
+    xt = np.random.default_rng(32).uniform(-1, 1, n)
+    xt[~refpy.active_mask(O.flags, O.st.nm)] = 0.0
+    xt[int(np.nonzero(O.flags & 8)[0][0])] = 0.0
+    b = oracle.apply(p.xf, p.yf, p.zf, O.flags, O.st, xt)
+    bd = torch.from_numpy(b).cuda()
+    nb = np.linalg.norm(b)
+    say("c3 fp64 solve")
+    x64, st64 = s64.solve_assembled(bd)
+    x64 = x64.cpu().numpy()
+    r64 = np.linalg.norm(b - oracle.apply(p.xf, p.yf, p.zf, O.flags, O.st, x64)) / nb
+    say("fp64: its %d, own residual %.2e, oracle residual %.2e, error %.2e" %
+        (st64.iterations, st64.rel_residual, r64, rel(x64, xt)))
+    assert st64.status == 0 and r64 <= 1.01e-12
+    del s64
+    torch.cuda.empty_cache()
+    smx = P.Solver(p.xf, p.yf, p.zf, flags, st, precision="mixed", tol=1e-12, max_iter=60, max_outer=20)
+    say("c3 mixed solve")
+    xm, stm = smx.solve_assembled(bd)
+    xm = xm.cpu().numpy()
+    rm = np.linalg.norm(b - oracle.apply(p.xf, p.yf, p.zf, O.flags, O.st, xm)) / nb
+    say("mixed: its %d outer %d, own residual %.2e, oracle residual %.2e, error %.2e, vs fp64 %.2e" %
+        (stm.iterations, stm.outer_steps, stm.rel_residual, rm, rel(xm, xt), rel(xm, x64)))
+    assert stm.status == 0 and rm <= 1.01e-12
+    # kappa ~ (12 / h_min^2) / (3 pi^2) ~ 3e5 on this grid bounds each error
+    # by kappa * residual (a 1e-8 solution match is not implied by any
+    # attainable residual here); iterative refinement must reach the FP64
+    # residual, so the mixed solution is held to the same bound
+    kappa = 3e5
+    assert rel(x64, xt) < kappa * 1e-12, rel(x64, xt)
+    assert rel(xm, xt) < kappa * 1e-12, rel(xm, xt)
+    assert rel(xm, x64) < kappa * 2e-12, rel(xm, x64)
