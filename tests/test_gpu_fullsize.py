@@ -114,3 +114,51 @@ def test_c3_manufactured_mixed_and_fp64(c3):
     assert rel(x64, xt) < kappa * 1e-12, rel(x64, xt)
     assert rel(xm, xt) < kappa * 1e-12, rel(xm, xt)
     assert rel(xm, x64) < kappa * 2e-12, rel(xm, x64)
+
+
+# ---------------------------------------------------------------- 1024^3, 20 spheres
+@pytest.fixture(scope="module")
+def c4():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_04335_amd as P
+    p = W.spheres_case(1024, rhs=False)
+    return P, p
+
+
+def test_c4_classification(c4):
+    """Largest configuration (1.07e9 cells): flags bit-exact against the oracle."""
+    P, p = c4
+    say("c4 classification")
+    flags, cst = P.classify(p.xf, p.yf, p.zf, p.bodies)
+    o = oracle.classify(p.xf, p.yf, p.zf, p.bodies)
+    g = flags.cpu().numpy()
+    assert np.array_equal(g, o), "mismatching cells: %d" % int(np.sum(g != o))
+    assert cst["n_ghost"] == int(np.sum((o & 2) > 0))
+
+
+def test_c4_manufactured_fp64(c4):
+    """b = A x_true on 1024^3: the FP64 solve meets 1e-11 and its error stays
+    within kappa * tol.  The pinned system's smallest singular value is set by
+    its single pin row, so kappa is well above the Laplacian's (12/h^2)/(3 pi^2)
+    ~ 4e5: the measured error/residual ratio at 1e-10 is 2.8e6."""
+    import torch
+    P, p = c4
+    flags, cst = P.classify(p.xf, p.yf, p.zf, p.bodies)
+    st = P.build_ghost_stencils(p.xf, p.yf, p.zf, p.bodies, flags)
+    sol = P.Solver(p.xf, p.yf, p.zf, flags, st, precision="fp64", tol=1e-11, max_iter=300)
+    fl = flags.cpu().numpy()
+    n = sol.n_unknowns
+    xt = np.random.default_rng(41).uniform(-1, 1, n)
+    xt[~refpy.active_mask(fl, sol.nm)] = 0.0
+    xt[int(np.nonzero(fl & 8)[0][0])] = 0.0
+    xd = torch.from_numpy(xt).cuda()
+    b = sol.apply(xd)
+    del xd
+    say("c4 fp64 solve")
+    x, stats = sol.solve_assembled(b)
+    err = float(torch.linalg.norm(x.cpu() - torch.from_numpy(xt)) / np.linalg.norm(xt))
+    say("c4 fp64: its %d residual %.2e error %.2e" % (stats.iterations, stats.rel_residual, err))
+    assert stats.status == 0 and stats.rel_residual <= 1e-11
+    assert err < 1e7 * 1e-11
