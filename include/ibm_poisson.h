@@ -162,6 +162,21 @@ void ibm_stencils_free(ibm_stencils *s);
 int32_t poisson_setup(const ibm_grid *grid, const uint8_t *flags_dev, const ibm_stencils *st,
                       const poisson_opts *opts, size_t *workspace_bytes, poisson_ctx **out);
 
+/*
+ * Caller-owned workspace.  poisson_workspace_size reports the bytes of the
+ * context's per-call scratch (Krylov vectors, multigrid iterates and
+ * right-hand sides -- everything but the operator tables, which stay
+ * library-owned).  poisson_bind_workspace moves that scratch into ws_dev
+ * (device memory of at least that size, 256-byte aligned, e.g. a torch uint8
+ * tensor): the library frees its own copies and never frees ws_dev, which
+ * must outlive the context or the next bind.  Contents of the scratch do not
+ * carry over between calls, so binding never changes results.  Returns
+ * IBM_ENOMEM when bytes is too small.  Not thread-safe with work in flight on
+ * the context.
+ */
+int32_t poisson_workspace_size(poisson_ctx *ctx, size_t *bytes);
+int32_t poisson_bind_workspace(poisson_ctx *ctx, void *ws_dev, size_t bytes);
+
 /* Device bytes a poisson_setup of this grid would hold (for admission). */
 int32_t poisson_workspace_estimate(int32_t nx, int32_t ny, int32_t nz, int64_t n_rows, int32_t precision,
                                    size_t *bytes);
@@ -220,15 +235,22 @@ void poisson_destroy(poisson_ctx *ctx);
  * below max_slots and the summed footprints (poisson_workspace_estimate plus
  * classification temporaries) fit hbm_budget; a request larger than the
  * whole budget fails with IBM_ENOMEM.  Finished solves release their slot and
- * memory at once.  Every solve is deterministic, so a result is the same
- * alone and in the mix.
+ * memory at once.  With cache_entries > 0 a finished solve's set-up
+ * (classification, ghost rows, operator, multigrid hierarchy) stays resident,
+ * keyed by the exact bytes of its grid, bodies and options: a later request
+ * with the same key reuses it and only runs the solve.  Cached set-ups count
+ * against hbm_budget and the least recently used idle ones are freed when an
+ * admission needs the memory.  Every solve is deterministic, so a result is
+ * the same alone, in the mix and from the cache.
  */
 typedef struct poisson_server poisson_server;
 
 typedef struct poisson_server_opts {
-    size_t hbm_budget;   /* bytes of device memory the active solves may hold */
-    int32_t max_slots;   /* concurrently active solves */
-    int32_t device;      /* HIP device ordinal */
+    size_t hbm_budget;      /* bytes of device memory the active solves (and cached hierarchies) may hold */
+    int32_t max_slots;      /* concurrently active solves */
+    int32_t device;         /* HIP device ordinal */
+    int32_t cache_entries;  /* solver set-ups kept after their solve, keyed by (grid, bodies, options);
+                               0 disables the cache */
 } poisson_server_opts;
 
 typedef struct poisson_request {
@@ -247,6 +269,8 @@ typedef struct poisson_request {
 typedef struct poisson_req_times {
     double submit_ms, admit_ms, done_ms; /* on the server's steady clock, from server start */
     int64_t n_unknowns;                  /* length of the solution once finished (N + n_mghost), else 0 */
+    int32_t cache_hit;                   /* 1: the request reused a cached set-up (no classification,
+                                            ghost rows or hierarchy build) */
 } poisson_req_times;
 
 int32_t poisson_server_create(const poisson_server_opts *opts, poisson_server **out);

@@ -64,7 +64,8 @@ class PoissonStats(ctypes.Structure):
 
 
 class _ServerOpts(ctypes.Structure):
-    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("device", ctypes.c_int32)]
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("cache_entries", ctypes.c_int32)]
 
 
 class _Request(ctypes.Structure):
@@ -74,14 +75,14 @@ class _Request(ctypes.Structure):
 
 class ReqTimes(ctypes.Structure):
     _fields_ = [("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
-                ("n_unknowns", ctypes.c_int64)]
+                ("n_unknowns", ctypes.c_int64), ("cache_hit", ctypes.c_int32)]
 
 
 EXPORTS = ["ibm_classify", "ibm_build_ghost_stencils", "ibm_stencils_info", "ibm_stencils_export",
            "ibm_stencils_free", "poisson_default_opts", "poisson_setup", "poisson_workspace_estimate",
            "poisson_solve", "poisson_apply", "poisson_assemble_rhs", "poisson_precond", "poisson_solve_assembled",
-           "poisson_destroy", "poisson_server_create", "poisson_submit", "poisson_poll", "poisson_server_drain",
-           "poisson_server_destroy", "ibm_last_error"]
+           "poisson_destroy", "poisson_workspace_size", "poisson_bind_workspace", "poisson_server_create",
+           "poisson_submit", "poisson_poll", "poisson_server_drain", "poisson_server_destroy", "ibm_last_error"]
 
 _lib = None
 
@@ -260,6 +261,19 @@ class Solver:
             _check(rc, "poisson_solve_assembled")
         return x, st
 
+    def workspace_size(self) -> int:
+        """Bytes of per-call scratch that bind_workspace can place in caller memory."""
+        b = ctypes.c_size_t()
+        _check(lib().poisson_workspace_size(self.h, ctypes.byref(b)), "poisson_workspace_size")
+        return b.value
+
+    def bind_workspace(self, ws):
+        """Place the scratch in a caller-owned device tensor (kept referenced here)."""
+        _check(lib().poisson_bind_workspace(self.h, ctypes.c_void_p(ws.data_ptr()),
+                                            ctypes.c_size_t(ws.numel() * ws.element_size())),
+               "poisson_bind_workspace")
+        self._ws = ws
+
     def apply(self, x, y=None):
         if y is None:
             y = self._vec(x.device)
@@ -312,10 +326,10 @@ def setup(xf, yf, zf, bodies, **opts):
 class Server:
     """Persistent continuous-batching solve server (one device)."""
 
-    def __init__(self, hbm_budget: int, max_slots: int = 16, device: int = 0):
+    def __init__(self, hbm_budget: int, max_slots: int = 16, device: int = 0, cache_entries: int = 8):
         self.h = ctypes.c_void_p()
         self._cells = {}
-        o = _ServerOpts(hbm_budget, max_slots, device)
+        o = _ServerOpts(hbm_budget, max_slots, device, cache_entries)
         _check(lib().poisson_server_create(ctypes.byref(o), ctypes.byref(self.h)), "poisson_server_create")
 
     def submit(self, xf, yf, zf, bodies, f, opts: Optional[PoissonOpts] = None, **kw) -> int:

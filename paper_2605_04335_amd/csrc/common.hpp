@@ -61,20 +61,29 @@ template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
+    bool own = true;  // false: a view into caller-owned memory (never freed here)
     DBuf() = default;
     explicit DBuf(size_t count) { alloc(count); }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), own(o.own) { o.p = nullptr; o.n = 0; }
     DBuf &operator=(DBuf &&o) noexcept
     {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) { release(); p = o.p; n = o.n; own = o.own; o.p = nullptr; o.n = 0; }
         return *this;
+    }
+    void view(T *q, size_t count)
+    {
+        release();
+        p = q;
+        n = count;
+        own = false;
     }
     ~DBuf() { release(); }
     void alloc(size_t count)
     {
         release();
+        own = true;
         n = count;
         if (count) {
             hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
@@ -89,9 +98,10 @@ struct DBuf {
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && own) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        own = true;
     }
     size_t bytes() const { return n * sizeof(T); }
 };

@@ -41,6 +41,8 @@ struct Request {
     std::vector<BodyCopy> bodies;
     std::vector<double> f;
     poisson_opts opts;
+    std::string key;            // exact bytes of grid, bodies and options
+    poisson_ctx *ctx = nullptr; // a cached set-up handed over at admission
     size_t footprint = 0;
     int state = IBM_REQ_QUEUED;
     int rc = IBM_OK;
@@ -49,6 +51,21 @@ struct Request {
     poisson_stats stats{};
     poisson_req_times times{};
 };
+
+// solver set-ups kept after their solve
+struct CacheEntry {
+    std::string key;
+    poisson_ctx *ctx = nullptr;
+    size_t bytes = 0;
+    uint64_t last = 0;
+    bool busy = false;
+};
+
+template <class T>
+void append_bytes(std::string &k, const T *p, size_t n)
+{
+    k.append(reinterpret_cast<const char *>(p), n * sizeof(T));
+}
 
 double now_ms(std::chrono::steady_clock::time_point t0)
 {
@@ -67,11 +84,45 @@ struct poisson_server {
     std::thread sched;
     size_t used = 0;
     int active = 0;
-    uint64_t next_id = 1;
+    uint64_t next_id = 1, tick = 0;
     bool stop = false;
+    std::vector<CacheEntry> cache;
 
     void run_request(Request *r);
     void schedule();
+    CacheEntry *find_idle(const std::string &key)
+    {
+        for (auto &e : cache)
+            if (!e.busy && e.key == key) return &e;
+        return nullptr;
+    }
+    size_t idle_bytes() const
+    {
+        size_t b = 0;
+        for (auto &e : cache)
+            if (!e.busy) b += e.bytes;
+        return b;
+    }
+    // free least recently used idle set-ups until `need` more bytes fit, or
+    // until at most `keep` entries remain (caller holds mu)
+    void evict(size_t need, size_t keep)
+    {
+        while (!cache.empty()) {
+            const bool over_budget = used + need > o.hbm_budget, over_count = cache.size() > keep;
+            if (!over_budget && !over_count) break;
+            int lru = -1;
+            for (int q = 0; q < (int)cache.size(); ++q)
+                if (!cache[q].busy && (lru < 0 || cache[q].last < cache[lru].last)) lru = q;
+            if (lru < 0) break;
+            poisson_destroy(cache[lru].ctx);
+            used -= cache[lru].bytes;
+            cache.erase(cache.begin() + lru);
+        }
+    }
+    ~poisson_server()
+    {
+        for (auto &e : cache) poisson_destroy(e.ctx);
+    }
 };
 
 void poisson_server::run_request(Request *r)
@@ -79,28 +130,31 @@ void poisson_server::run_request(Request *r)
     int rc = IBM_OK;
     std::string err;
     hipStream_t s = nullptr;
+    poisson_ctx *keep = nullptr;  // set-up to cache after the solve
     try {
         IBM_HIP(hipSetDevice(o.device));
         IBM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         ibm_grid g{r->g.n[0], r->g.n[1], r->g.n[2], r->g.f[0].data(), r->g.f[1].data(), r->g.f[2].data()};
-        std::vector<ibm_body> bd;
-        for (auto &b : r->bodies)
-            bd.push_back(ibm_body{(int32_t)(b.v.size() / 3), (int32_t)(b.t.size() / 3), b.kind, b.v.data(), b.t.data()});
         const long long N = (long long)g.nx * g.ny * g.nz;
-        DBuf<uint8_t> flags(N);
-        classify(&g, bd.data(), (int)bd.size(), flags.p, nullptr, s);
-        ibm_stencils *st = nullptr;
-        build_stencils(&g, bd.data(), (int)bd.size(), flags.p, &st, s);
-        std::unique_ptr<ibm_stencils> stg(st);
-        const long long nm = st->nm;
-        poisson_ctx *ctx = nullptr;
-        size_t bytes = 0;
-        int e = poisson_setup(&g, flags.p, st, &r->opts, &bytes, &ctx);
-        if (e) throw Error(e, ibm_last_error());
+        poisson_ctx *ctx = r->ctx;
+        if (!ctx) {
+            std::vector<ibm_body> bd;
+            for (auto &b : r->bodies)
+                bd.push_back(
+                    ibm_body{(int32_t)(b.v.size() / 3), (int32_t)(b.t.size() / 3), b.kind, b.v.data(), b.t.data()});
+            DBuf<uint8_t> flags(N);
+            classify(&g, bd.data(), (int)bd.size(), flags.p, nullptr, s);
+            ibm_stencils *st = nullptr;
+            build_stencils(&g, bd.data(), (int)bd.size(), flags.p, &st, s);
+            std::unique_ptr<ibm_stencils> stg(st);
+            size_t bytes = 0;
+            int e = poisson_setup(&g, flags.p, st, &r->opts, &bytes, &ctx);
+            if (e) throw Error(e, ibm_last_error());
+        }
         std::unique_ptr<poisson_ctx, void (*)(poisson_ctx *)> cg(ctx, poisson_destroy);
-        stg.reset();
-        flags.release();
-        const long long nt = N + nm;
+        int64_t nun = 0;
+        IBM_REQUIRE(poisson_level_info(ctx, nullptr, &nun, nullptr, nullptr) == IBM_OK, IBM_EINVAL, "level info");
+        const long long nt = nun;
         DBuf<double> df(N), dx(nt);
         IBM_HIP(hipMemcpyAsync(df.p, r->f.data(), N * 8, hipMemcpyHostToDevice, s));
         rc = poisson_solve(ctx, df.p, nullptr, dx.p, &r->stats, s);
@@ -108,6 +162,7 @@ void poisson_server::run_request(Request *r)
         r->x.resize(nt);
         IBM_HIP(hipMemcpyAsync(r->x.data(), dx.p, nt * 8, hipMemcpyDeviceToHost, s));
         IBM_HIP(hipStreamSynchronize(s));
+        if (o.cache_entries > 0) keep = cg.release();
     } catch (const Error &e) {
         rc = e.code;
         err = e.what();
@@ -122,7 +177,26 @@ void poisson_server::run_request(Request *r)
     r->stats.status = rc;
     r->state = rc == IBM_OK || rc == IBM_ENOCONV ? IBM_REQ_DONE : IBM_REQ_FAILED;
     r->times.done_ms = now_ms(t0);
-    used -= r->footprint;
+    if (r->ctx) {
+        // a cached set-up: back to idle (its memory stays accounted), or gone
+        // if the solve failed
+        for (size_t q = 0; q < cache.size(); ++q)
+            if (cache[q].ctx == r->ctx) {
+                if (keep) { cache[q].busy = false; cache[q].last = ++tick; }
+                else { used -= cache[q].bytes; cache.erase(cache.begin() + q); }
+                break;
+            }
+    } else if (keep) {
+        CacheEntry e;
+        e.key = r->key;
+        e.ctx = keep;
+        e.bytes = r->footprint;  // stays accounted while cached
+        e.last = ++tick;
+        cache.push_back(std::move(e));
+        evict(0, (size_t)o.cache_entries);
+    } else {
+        used -= r->footprint;
+    }
     --active;
     cv.notify_all();
 }
@@ -135,7 +209,9 @@ void poisson_server::schedule()
             if (stop) return true;
             if (queue.empty()) return false;
             Request *h = queue.front();
-            return h->footprint > o.hbm_budget || (active < o.max_slots && used + h->footprint <= o.hbm_budget);
+            if (h->footprint > o.hbm_budget) return true;
+            if (active >= o.max_slots) return false;
+            return find_idle(h->key) != nullptr || used - idle_bytes() + h->footprint <= o.hbm_budget;
         });
         if (stop && queue.empty()) break;
         if (stop) {  // refuse what is still queued
@@ -159,7 +235,14 @@ void poisson_server::schedule()
             cv.notify_all();
             continue;
         }
-        used += r->footprint;
+        if (CacheEntry *e = find_idle(r->key)) {
+            e->busy = true;
+            r->ctx = e->ctx;
+            r->times.cache_hit = 1;
+        } else {
+            evict(r->footprint, (size_t)o.cache_entries);
+            used += r->footprint;
+        }
         ++active;
         r->state = IBM_REQ_RUNNING;
         r->times.admit_ms = now_ms(t0);
@@ -198,6 +281,22 @@ extern "C" int32_t poisson_submit(poisson_server *S, const poisson_request *q, u
         const long long N = (long long)r->g.n[0] * r->g.n[1] * r->g.n[2];
         r->f.assign(q->f, q->f + N);
         r->opts = q->opts;
+        append_bytes(r->key, r->g.n, 3);
+        for (int d = 0; d < 3; ++d) append_bytes(r->key, r->g.f[d].data(), r->g.f[d].size());
+        for (auto &b : r->bodies) {
+            append_bytes(r->key, &b.kind, 1);
+            const size_t nv = b.v.size(), nt = b.t.size();
+            append_bytes(r->key, &nv, 1);
+            append_bytes(r->key, b.v.data(), nv);
+            append_bytes(r->key, &nt, 1);
+            append_bytes(r->key, b.t.data(), nt);
+        }
+        const poisson_opts &po = r->opts;  // field by field: no padding bytes in the key
+        const double od[2] = {po.tol, po.inner_tol};
+        const int32_t oi[7] = {po.precision, po.max_iter, po.nu1, po.nu2, po.coarse_sweeps, po.max_outer,
+                               po.use_graph};
+        append_bytes(r->key, od, 2);
+        append_bytes(r->key, oi, 7);
         // footprint: solver workspace plus classification temporaries, with a
         // generous bound on the ghost rows (one cell in eight)
         r->footprint = estimate_bytes(r->g.n[0], r->g.n[1], r->g.n[2], N / 8, q->opts.precision) + (size_t)N +

@@ -1137,6 +1137,64 @@ extern "C" int32_t poisson_level_info(poisson_ctx *c, int32_t *levels, int64_t *
     });
 }
 
+namespace ibm {
+namespace {
+// the context's large per-call scratch (Krylov vectors, level iterates and
+// right-hand sides): every buffer currently held, in a fixed order
+template <class F>
+void for_scratch(poisson_ctx &c, F &&f)
+{
+    DBuf<double> *d[] = {&c.x, &c.r, &c.b, &c.t, &c.rh, &c.p, &c.v, &c.ph, &c.sh, &c.rsp, &c.d64, &c.r2};
+    for (auto *q : d) f(*q);
+    DBuf<float> *fl[] = {&c.fr, &c.frh, &c.fp, &c.fv, &c.fph, &c.fsh, &c.ft, &c.frsp};
+    for (auto *q : fl) f(*q);
+    for (size_t l = 1; l < c.lv.size(); ++l) {
+        f(c.lv[l].x64);
+        f(c.lv[l].b64);
+        f(c.lv[l].x32);
+        f(c.lv[l].b16);
+    }
+}
+constexpr size_t WS_ALIGN = 256;
+size_t ws_round(size_t b) { return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
+}  // namespace
+}  // namespace ibm
+
+extern "C" int32_t poisson_workspace_size(poisson_ctx *c, size_t *bytes)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c && bytes, IBM_EINVAL, "null argument");
+        size_t total = 0;
+        for_scratch(*c, [&](auto &b) { total += ws_round(b.bytes()); });
+        *bytes = total;
+    });
+}
+
+extern "C" int32_t poisson_bind_workspace(poisson_ctx *c, void *ws_dev, size_t bytes)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c && ws_dev, IBM_EINVAL, "null argument");
+        IBM_REQUIRE(((uintptr_t)ws_dev % WS_ALIGN) == 0, IBM_EINVAL, "workspace must be 256-byte aligned");
+        size_t need = 0;
+        for_scratch(*c, [&](auto &b) { need += ws_round(b.bytes()); });
+        IBM_REQUIRE(bytes >= need, IBM_ENOMEM, "workspace too small: " + std::to_string(bytes) + " < " +
+                                                   std::to_string(need));
+        IBM_HIP(hipStreamSynchronize(c->cs));
+        // captured iterations hold the old addresses
+        if (c->g64) { (void)hipGraphExecDestroy(c->g64); c->g64 = nullptr; }
+        if (c->g32) { (void)hipGraphExecDestroy(c->g32); c->g32 = nullptr; }
+        char *base = (char *)ws_dev;
+        size_t off = 0;
+        for_scratch(*c, [&](auto &b) {
+            if (!b.n) return;
+            const size_t n = b.n, sz = ws_round(b.bytes());
+            typedef typename std::remove_reference<decltype(*b.p)>::type E;
+            b.view(reinterpret_cast<E *>(base + off), n);
+            off += sz;
+        });
+    });
+}
+
 extern "C" void poisson_destroy(poisson_ctx *c)
 {
     if (c) {

@@ -249,3 +249,25 @@ def test_error_paths(torch_cuda):
     f[5] = float("nan")
     x, stats = sol.solve(f, check=False)
     assert stats.status in (P.IBM_EBREAKDOWN, P.IBM_ENOCONV)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_caller_owned_workspace(torch_cuda, precision):
+    """Scratch moved into a caller tensor gives bitwise the same solution; a
+    too-small workspace is refused."""
+    import paper_2605_04335_amd as P
+    torch = torch_cuda
+    p = CASES["membrane_64"]
+    f = torch.from_numpy(p.f).cuda()
+    _, _, s1, _ = gpu_setup(torch, p, precision=precision, tol=1e-10)
+    x1, st1 = s1.solve(f)
+    _, _, s2, _ = gpu_setup(torch, p, precision=precision, tol=1e-10)
+    nb = s2.workspace_size()
+    assert nb > 0
+    with pytest.raises(P.IbmError) as e:
+        s2.bind_workspace(torch.empty(nb // 2, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == P.IBM_ENOMEM
+    s2.bind_workspace(torch.empty(nb, dtype=torch.uint8, device="cuda"))
+    x2, st2 = s2.solve(f)
+    assert st2.iterations == st1.iterations
+    assert torch.equal(x1, x2)

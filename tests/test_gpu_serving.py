@@ -139,3 +139,48 @@ def test_poll_states(P):
         srv.drain()
     finally:
         srv.close()
+
+
+def test_setup_cache(P):
+    """A repeated (grid, bodies, options) request reuses the cached set-up and
+    returns bitwise the same solution; an admission that needs the memory
+    evicts the idle set-up."""
+    a, b = requests(2, 14, 48, 64)
+    opts = dict(precision="mixed", tol=1e-8)
+
+    srv = P.Server(hbm_budget=16 << 30, max_slots=2, cache_entries=4)
+    try:
+        ta = srv.submit(a.xf, a.yf, a.zf, a.bodies, a.f, **opts)
+        r1 = wait_all(P, srv, [ta])[ta]
+        tb = srv.submit(a.xf, a.yf, a.zf, a.bodies, a.f, **opts)
+        # poll by hand to read the cache flag
+        while True:
+            rc, state, x2, st2, tm2 = srv.poll(tb)
+            if rc != P.IBM_EAGAIN:
+                break
+            time.sleep(0.002)
+        assert r1[0] == P.IBM_OK and rc == P.IBM_OK
+        assert tm2.cache_hit == 1
+        assert np.array_equal(r1[2], x2)
+    finally:
+        srv.close()
+    # a budget that holds one set-up (the server's footprint: workspace plus
+    # classification temporaries): b evicts a's cached set-up and vice versa
+    fa, fb = (P.workspace_estimate(*q.shape, q.npts // 8, "mixed") + int(17.5 * q.npts) for q in (a, b))
+    assert min(fa, fb) > 0.1 * max(fa, fb)
+    srv = P.Server(hbm_budget=int(1.1 * max(fa, fb)), max_slots=1, cache_entries=4)
+    try:
+        hits = []
+        for p in (a, b, a):
+            t = srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, **opts)
+            while True:
+                rc, state, x, st, tm = srv.poll(t)
+                if rc != P.IBM_EAGAIN:
+                    break
+                time.sleep(0.002)
+            assert rc == P.IBM_OK
+            hits.append(tm.cache_hit)
+        say("cache hits", hits)
+        assert hits == [0, 0, 0]
+    finally:
+        srv.close()
