@@ -220,6 +220,60 @@ def solve(xf, yf, zf, flags, st: Stencils, b, tol=1e-10, maxit=200, x0=None, nu1
     return x, SolveInfo(rc, it, float(info[1]), int(info[2]), hist[:it].copy())
 
 
+def srj_schedule(m: int, kmin: float = None) -> np.ndarray:
+    """Relaxation factors of an m-sweep scheduled-relaxation Jacobi schedule.
+
+    The amplification of a mode with eigenvalue k of D^-1 A (k in (0, 2] for
+    this operator) after the schedule is prod_s (1 - w_s k); the factors that
+    minimise its maximum over [kmin, 2] are the reciprocals of the roots of
+    the degree-m Chebyshev polynomial mapped onto that interval.  They are
+    applied smallest, largest, second smallest, ... so that partial products
+    stay bounded.  kmin defaults to 16 / m^2 (smaller values make the largest
+    factors grow like 1/kmin and the schedule sensitive to rounding).
+    """
+    if kmin is None:
+        kmin = 16.0 / (m * m)
+    j = np.arange(1, m + 1)
+    kap = 0.5 * (2.0 + kmin) - 0.5 * (2.0 - kmin) * np.cos(np.pi * (2 * j - 1) / (2.0 * m))
+    w = np.sort(1.0 / kap)
+    order = []
+    lo, hi = 0, m - 1
+    while lo <= hi:
+        order.append(lo)
+        if hi != lo:
+            order.append(hi)
+        lo += 1
+        hi -= 1
+    return np.ascontiguousarray(w[order])
+
+
+def srj(xf, yf, zf, flags, st: Stencils, b, omega, pinned=True, shift=True) -> np.ndarray:
+    """len(omega) SRJ sweeps from zero on A x = b (optionally shifted like the V-cycle output)."""
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    b = _f64(b)
+    om = _f64(omega)
+    x = np.zeros_like(b)
+    keep, a = _sys_args(xf, yf, zf, flags, st)
+    lib().orc_srj(*a, ctypes.c_int(1 if pinned else 0), ctypes.c_int(1 if shift else 0), ctypes.c_int(len(om)),
+                  _p(om), _p(b), _p(x))
+    return x
+
+
+def solve_srj(xf, yf, zf, flags, st: Stencils, b, omega, tol=1e-10, maxit=500, x0=None):
+    """SRJ-preconditioned BiCGSTAB on the pinned system; returns (x, info)."""
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    b = _f64(b)
+    om = _f64(omega)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    info = np.zeros(3)
+    hist = np.zeros(maxit + 1)
+    keep, a = _sys_args(xf, yf, zf, flags, st)
+    rc = lib().orc_solve_srj(*a, _p(b), _p(x), ctypes.c_double(tol), ctypes.c_int(maxit), ctypes.c_int(len(om)),
+                             _p(om), _p(info), _p(hist))
+    it = int(info[0])
+    return x, SolveInfo(rc, it, float(info[1]), int(info[2]), hist[:it].copy())
+
+
 # --------------------------------------------------------------------------
 @dataclass
 class Setup:

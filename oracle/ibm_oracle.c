@@ -1185,23 +1185,96 @@ int orc_num_levels(int nx, int ny, int nz)
 }
 
 /*
- * Right-preconditioned BiCGSTAB (van der Vorst 1992) with the V-cycle as
- * preconditioner, on the pinned system.  x holds the initial guess on entry
- * and the solution on exit.  Stops when the recursive relative residual is
- * at most tol and the true one confirms it (else the true residual replaces
- * the recursive one).  If precond is 0 the preconditioner is the identity.
+ * Scheduled relaxation Jacobi (SRJ), the PPE preconditioner of the paper
+ * (Sec. 2.1): m weighted-Jacobi sweeps x <- x + omega_s D^{-1} (b - A x)
+ * from x = 0, all rows at once, with D the diagonal of the operator (fluid
+ * and pin rows: minus the sum of their face coefficients; ghost rows: -sG).
+ * pinned = 0 uses the singular operator (the pin row an ordinary fluid row).
+ * shift != 0 then moves the result into the pinned subspace exactly as the
+ * V-cycle does (active values and ghost unknowns minus the pin value).
+ */
+typedef struct {
+    int m;
+    const double *omega;
+    double *dinv, *y;
+} SRJ;
+
+static void srj_init(SRJ *R, const Sys *S, int m, const double *omega)
+{
+    const Grid *g = &S->g;
+    int64_t n = S->N + S->nm;
+    R->m = m;
+    R->omega = omega;
+    R->dinv = calloc(n, 8);
+    R->y = malloc(8 * n);
+    for (int k = 0; k < g->n[2]; ++k)
+        for (int j = 0; j < g->n[1]; ++j)
+            for (int i = 0; i < g->n[0]; ++i) {
+                int64_t p = IDX(g->n, i, j, k);
+                if (!(S->flags[p] & F_SOLID)) R->dinv[p] = -1.0 / cell_scale(g, i, j, k);
+            }
+    for (int32_t r = 0; r < S->ng + S->nm; ++r) R->dinv[row_unknown(S, r)] = -1.0 / S->sG[r];
+}
+
+static void srj_free(SRJ *R)
+{
+    free(R->dinv);
+    free(R->y);
+}
+
+static void srj_apply(const SRJ *R, const Sys *S, int pinned, int shift, const double *b, double *x)
+{
+    int64_t n = S->N + S->nm;
+    memset(x, 0, 8 * n);
+    for (int s = 0; s < R->m; ++s) {
+        sys_apply_m(S, x, R->y, pinned);
+        const double om = R->omega[s];
+#pragma omp parallel for
+        for (int64_t q = 0; q < n; ++q) x[q] += om * R->dinv[q] * (b[q] - R->y[q]);
+    }
+    if (shift) {
+        double c = x[S->pin];
+        for (int64_t p = 0; p < S->N; ++p)
+            if (!(S->flags[p] & F_SOLID) || (S->flags[p] & F_GHOST)) x[p] -= c;
+        for (int32_t m = 0; m < S->nm; ++m) x[S->N + m] -= c;
+    }
+}
+
+void orc_srj(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, const uint8_t *flags,
+             const int32_t *mg_of, int32_t ng, int32_t nm, const int32_t *row_cell, const int32_t *col,
+             const double *w, const double *sG, int pinned, int shift, int m, const double *omega, const double *b,
+             double *x)
+{
+    Sys S;
+    if (sys_init(&S, nx, ny, nz, xf, yf, zf, flags, mg_of, ng, nm, row_cell, col, w, sG)) return;
+    SRJ R;
+    srj_init(&R, &S, m, omega);
+    srj_apply(&R, &S, pinned, shift, b, x);
+    srj_free(&R);
+    grid_free(&S.g);
+}
+
+/*
+ * Right-preconditioned BiCGSTAB (van der Vorst 1992) on the pinned system,
+ * preconditioned by the V-cycle (precond 1), by SRJ (precond 2) or by the
+ * identity (precond 0).  x holds the initial guess on entry and the solution
+ * on exit.  Stops when the recursive relative residual is at most tol and the
+ * true one confirms it (else the true residual replaces the recursive one).
  * info[0] iterations, info[1] true relative residual, info[2] restarts.
  */
-int orc_solve(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, const uint8_t *flags,
-              const int32_t *mg_of, int32_t ng, int32_t nm, const int32_t *row_cell, const int32_t *col,
-              const double *w, const double *sG, const double *b, double *x, double tol, int maxit, int nu1, int nu2,
-              int ncs, int precond, double *info, double *hist)
+static int solve_impl(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
+                      const uint8_t *flags, const int32_t *mg_of, int32_t ng, int32_t nm, const int32_t *row_cell,
+                      const int32_t *col, const double *w, const double *sG, const double *b, double *x, double tol,
+                      int maxit, int nu1, int nu2, int ncs, int precond, int srj_m, const double *srj_omega,
+                      double *info, double *hist)
 {
     Sys S;
     if (sys_init(&S, nx, ny, nz, xf, yf, zf, flags, mg_of, ng, nm, row_cell, col, w, sG)) return ORC_EINVAL;
     int64_t n = S.N + nm;
     MG M;
-    if (precond) mg_build(&M, &S, nu1, nu2, ncs);
+    SRJ R;
+    if (precond == 1) mg_build(&M, &S, nu1, nu2, ncs);
+    if (precond == 2) srj_init(&R, &S, srj_m, srj_omega);
     double *r = malloc(8 * n), *rh = malloc(8 * n), *p = calloc(n, 8), *v = calloc(n, 8), *ph = malloc(8 * n),
            *s = malloc(8 * n), *sh = malloc(8 * n), *t = malloc(8 * n);
     sys_apply(&S, x, r);
@@ -1232,13 +1305,17 @@ int orc_solve(int nx, int ny, int nz, const double *xf, const double *yf, const 
             beta = (rho / rho_old) * (alpha / omega);
         }
         for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
-        if (precond) vcycle(&M, p, ph); else memcpy(ph, p, 8 * n);
+        if (precond == 1) vcycle(&M, p, ph);
+        else if (precond == 2) srj_apply(&R, &S, 1, 1, p, ph);
+        else memcpy(ph, p, 8 * n);
         sys_apply(&S, ph, v);
         double rv = dotv(rh, v, n);
         if (rv == 0.0 || !isfinite(rv)) { rc = ORC_EBREAKDOWN; break; }
         alpha = rho / rv;
         for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
-        if (precond) vcycle(&M, s, sh); else memcpy(sh, s, 8 * n);
+        if (precond == 1) vcycle(&M, s, sh);
+        else if (precond == 2) srj_apply(&R, &S, 1, 1, s, sh);
+        else memcpy(sh, s, 8 * n);
         sys_apply(&S, sh, t);
         double tt = dotv(t, t, n), ts = dotv(t, s, n);
         omega = tt > 0.0 ? ts / tt : 0.0;
@@ -1270,9 +1347,29 @@ done:
         info[2] = restarts;
     }
     free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t);
-    if (precond) mg_free(&M);
+    if (precond == 1) mg_free(&M);
+    if (precond == 2) srj_free(&R);
     grid_free(&S.g);
     return rc;
+}
+
+int orc_solve(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, const uint8_t *flags,
+              const int32_t *mg_of, int32_t ng, int32_t nm, const int32_t *row_cell, const int32_t *col,
+              const double *w, const double *sG, const double *b, double *x, double tol, int maxit, int nu1, int nu2,
+              int ncs, int precond, double *info, double *hist)
+{
+    return solve_impl(nx, ny, nz, xf, yf, zf, flags, mg_of, ng, nm, row_cell, col, w, sG, b, x, tol, maxit, nu1, nu2,
+                      ncs, precond ? 1 : 0, 0, NULL, info, hist);
+}
+
+/* BiCGSTAB preconditioned by SRJ (m sweeps with the given schedule). */
+int orc_solve_srj(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf,
+                  const uint8_t *flags, const int32_t *mg_of, int32_t ng, int32_t nm, const int32_t *row_cell,
+                  const int32_t *col, const double *w, const double *sG, const double *b, double *x, double tol,
+                  int maxit, int m, const double *omega, double *info, double *hist)
+{
+    return solve_impl(nx, ny, nz, xf, yf, zf, flags, mg_of, ng, nm, row_cell, col, w, sG, b, x, tol, maxit, 0, 0, 0,
+                      2, m, omega, info, hist);
 }
 
 #ifdef _OPENMP

@@ -384,3 +384,77 @@ def test_p5_flat_membrane_equals_masked_faces():
     xm = spsolve(A.tocsc(), bb)
     xm -= np.sum(vol * xm) / np.sum(vol)
     assert rel(x[:S.N], xm) < 1e-10
+
+
+# ---------------------------------------------------------------- P11: SRJ preconditioner
+def _srj_case():
+    f = W.uniform_faces(12)
+    bodies = [W.sphere((0.5, 0.5, 0.5), 0.3, freq=4)]
+    return f, f, f, bodies
+
+
+@pytest.mark.parametrize("pinned", [True, False])
+def test_p11_srj_matches_dense_jacobi(pinned):
+    """m weighted-Jacobi sweeps on the independently assembled matrix."""
+    xf, yf, zf, bodies = _srj_case()
+    S = setup_problem(xf, yf, zf, bodies)
+    A = refpy.assemble(xf, yf, zf, S.flags, S.st, pinned=pinned).tocsr()
+    d = A.diagonal()
+    n = S.N + S.st.nm
+    rng = np.random.default_rng(11)
+    b = rng.uniform(-1, 1, n)
+    b[~refpy.active_mask(S.flags, S.st.nm)] = 0.0
+    om = oracle.srj_schedule(8)
+    x = np.zeros(n)
+    nz = d != 0
+    for w in om:
+        r = b - A @ x
+        x[nz] += w * r[nz] / d[nz]
+    xo = oracle.srj(xf, yf, zf, S.flags, S.st, b, om, pinned=pinned, shift=False)
+    assert rel(xo, x) < 1e-13
+    # the shifted form: active values and ghost unknowns minus the pin value
+    xs = oracle.srj(xf, yf, zf, S.flags, S.st, b, om, pinned=pinned, shift=True)
+    pin = int(np.nonzero(S.flags & 8)[0][0])
+    act = refpy.active_mask(S.flags, S.st.nm)
+    ref = x.copy()
+    ref[act] -= x[pin]
+    assert rel(xs, ref) < 1e-13
+
+
+@pytest.mark.parametrize("m", [8, 16])
+def test_p11_srj_schedule_is_minimax(m):
+    """The schedule's amplification prod (1 - w k) equioscillates on [kmin, 2]
+    with the Chebyshev minimax value 1 / T_m((2 + kmin) / (2 - kmin))."""
+    om = oracle.srj_schedule(m)
+    kmin = 16.0 / (m * m)
+    k = np.linspace(kmin, 2.0, 400001)
+    G = np.ones_like(k)
+    for w in om:
+        G *= 1.0 - w * k
+    bound = 1.0 / np.cosh(m * np.arccosh((2.0 + kmin) / (2.0 - kmin)))
+    assert abs(np.abs(G).max() / bound - 1.0) < 1e-6
+    assert int(np.sum(np.diff(np.sign(G)) != 0)) == m
+    # below kmin the amplification stays in (0, 1): the preconditioned spectrum is positive
+    k0 = np.linspace(1e-6, kmin, 1001)
+    G0 = np.ones_like(k0)
+    for w in om:
+        G0 *= 1.0 - w * k0
+    assert np.all(G0 > 0) and np.all(G0 < 1)
+
+
+@pytest.mark.parametrize("case", ["sphere12", "membrane"])
+def test_p11_srj_bicgstab_matches_direct(case):
+    if case == "sphere12":
+        xf, yf, zf, bodies = _srj_case()
+    else:
+        xf, _ = W.stretched_faces(14)
+        yf, zf = W.uniform_faces(12), W.uniform_faces(12)
+        bodies = [W.plate((0.5, 0.5, 0.5), 0.4, 0.6, 6, 9, 0.06, 0.9)]
+    S = setup_problem(xf, yf, zf, bodies)
+    A = refpy.assemble(xf, yf, zf, S.flags, S.st)
+    rhs = W.noise_rhs(S.N, 12)
+    b = oracle.assemble_rhs(xf, yf, zf, S.flags, S.st, rhs)
+    x, info = oracle.solve_srj(xf, yf, zf, S.flags, S.st, b, oracle.srj_schedule(16), tol=1e-13, maxit=500)
+    assert info.rc == 0
+    xd = refpy.solve_direct(A, b, S.flags, S.st.nm)
+    assert rel(x, xd) < 1e-10
