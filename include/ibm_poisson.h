@@ -76,6 +76,21 @@ typedef struct poisson_ctx poisson_ctx;   /* opaque, library-owned */
 #define IBM_PREC_FP64 0
 #define IBM_PREC_MIXED 1
 
+/* Preconditioner of the BiCGSTAB iteration.  MG: the geometric-multigrid
+ * V-cycle (default).  SRJ: scheduled relaxation Jacobi, the preconditioner
+ * the paper pairs with BiCGStab for the PPE (Sec. 2.1): srj_sweeps weighted
+ * Jacobi sweeps from zero with relaxation factors 1/k_s, k_s the roots of the
+ * degree-srj_sweeps Chebyshev polynomial on [16/srj_sweeps^2, 2] (the
+ * minimax schedule for the amplification over the spectrum of D^-1 A),
+ * applied smallest, largest, second smallest, ...  srj_sweeps is limited to
+ * 1..IBM_SRJ_MAX_SWEEPS (IBM_EINVAL otherwise): the Neumann ghost rows give
+ * D^-1 A modes, localised at the ghost cells and their fluid neighbours, that
+ * longer schedules (largest factor ~ srj_sweeps^2 / 16) amplify instead of
+ * damp on grids of 128^3 and more. */
+#define IBM_PRECOND_MG 0
+#define IBM_PRECOND_SRJ 1
+#define IBM_SRJ_MAX_SWEEPS 16
+
 typedef struct poisson_opts {
     int32_t precision;      /* IBM_PREC_FP64 or IBM_PREC_MIXED */
     double tol;             /* relative true residual ||b - A x|| / ||b|| */
@@ -85,6 +100,8 @@ typedef struct poisson_opts {
     double inner_tol;       /* mixed: relative tolerance of each inner solve */
     int32_t max_outer;      /* mixed: outer refinement steps */
     int32_t use_graph;      /* replay each iteration as a captured HIP graph */
+    int32_t precond;        /* IBM_PRECOND_MG or IBM_PRECOND_SRJ */
+    int32_t srj_sweeps;     /* SRJ: Jacobi sweeps per preconditioner application */
 } poisson_opts;
 
 typedef struct poisson_stats {
@@ -99,11 +116,15 @@ typedef struct poisson_stats {
 } poisson_stats;
 
 /* Defaults: FP64, tol 1e-10, 200 iterations, V(2,2), 32 coarse sweeps,
- * inner_tol 1e-3, max_outer 10, graphs on.  Each inner solve of the mixed
+ * inner_tol 1e-3, max_outer 10, graphs on, multigrid preconditioner
+ * (srj_sweeps 16 when SRJ is chosen).  Each inner solve of the mixed
  * form asks for max(inner_tol, tol / (2 rel)) where rel is the current FP64
  * relative residual: tighter inner tolerances buy little, because the BF16
  * rounding of the coarse right-hand sides makes the preconditioner slightly
- * non-linear and the inner Krylov iteration slows down below ~1e-3. */
+ * non-linear and the inner Krylov iteration slows down below ~1e-3.
+ * Refinement switches to an FP64 BiCGSTAB on the remaining residual when an
+ * outer step makes the FP64 residual larger (that step is undone) or when an
+ * inner solve stops at max_iter before its tolerance. */
 void poisson_default_opts(poisson_opts *opts);
 
 /*

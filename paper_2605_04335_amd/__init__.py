@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libibmpoisson.so")
 IBM_OK, IBM_EINVAL, IBM_EGEOM, IBM_ENOMEM, IBM_EHIP, IBM_ENOCONV, IBM_EBREAKDOWN, IBM_EAGAIN, IBM_ENOTFOUND = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC_FP64, PREC_MIXED = 0, 1
+PRECOND_MG, PRECOND_SRJ = 0, 1
+SRJ_MAX_SWEEPS = 16
 IBM_REQ_QUEUED, IBM_REQ_RUNNING, IBM_REQ_DONE, IBM_REQ_FAILED = 0, 1, 2, 3
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
@@ -51,7 +53,8 @@ class _ClassStats(ctypes.Structure):
 class PoissonOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("srj_sweeps", ctypes.c_int32)]
 
 
 class PoissonStats(ctypes.Structure):
@@ -155,6 +158,8 @@ def default_opts(**kw) -> PoissonOpts:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = PREC_MIXED if v == "mixed" else PREC_FP64
+        if k == "precond" and isinstance(v, str):
+            v = PRECOND_SRJ if v == "srj" else PRECOND_MG
         setattr(o, k, v)
     return o
 

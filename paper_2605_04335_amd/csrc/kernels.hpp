@@ -632,6 +632,78 @@ __global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, con
     }
 }
 
+// One weighted-Jacobi sweep of the pinned system on the regular level-0
+// rows of both colours: xn = xo + w (b - A xo) / diag(A), diag = -(sum of the
+// face coefficients); solid cells and padding get 0; ghost and membrane rows
+// are left to k0_jacobi_sparse.  Every row reads xo only.
+template <class T>
+__global__ void __launch_bounds__(TPB) k0_jacobi(Lv L, Geo G, long long pin, const T *__restrict__ xo,
+                                                 T *__restrict__ xn, const T *__restrict__ b, double w)
+{
+    int h, j, k0, k1;
+    if (!geo_tile(G, h, j, k0, k1)) return;
+    const long long pl = (long long)L.H * L.ny, Nh = L.Nh;
+    const long long col = h + (long long)L.H * j;
+    const Col0 q0 = col0(L, 0, h, j), q1 = col0(L, 1, h, j);
+    constexpr int UJ = 2;
+    for (int kb = k0; kb < k1; kb += UJ) {
+        uint8_t f[UJ][2];
+        double xv[UJ][2], nb[UJ][2], dg[UJ][2], bv[UJ][2];
+#pragma unroll
+        for (int u = 0; u < UJ; ++u) {
+            const int k = min(kb + u, k1 - 1);
+            const long long s = col + pl * k, t = Nh + s;
+            f[u][0] = L.f[s];
+            f[u][1] = L.f[t];
+            xv[u][0] = ld(xo, s);
+            xv[u][1] = ld(xo, t);
+            nb[u][0] = col0_sum(L, q0, xo + Nh, s, k, pl, dg[u][0]);
+            nb[u][1] = col0_sum(L, q1, xo, s, k, pl, dg[u][1]);
+            bv[u][0] = ld(b, s);
+            bv[u][1] = ld(b, t);
+        }
+#pragma unroll
+        for (int u = 0; u < UJ; ++u) {
+            if (kb + u >= k1) continue;
+            const long long s0 = col + pl * (kb + u);
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                const long long sc = s0 + (cc ? Nh : 0);
+                const uint8_t ff = f[u][cc];
+                if (ff & F_MGHOST) continue;
+                if (ff & F_SOLID) {
+                    if (!(ff & F_GHOST)) st(xn, sc, 0.0);
+                    continue;
+                }
+                const double ax = sc == pin ? -dg[u][cc] * xv[u][cc] : nb[u][cc] - dg[u][cc] * xv[u][cc];
+                st(xn, sc, xv[u][cc] + w * (bv[u][cc] - ax) / (-dg[u][cc]));
+            }
+        }
+    }
+}
+
+// the same sweep on the ghost rows (diag -sG) and the membrane rows
+template <class T>
+__global__ void __launch_bounds__(TPB) k0_jacobi_sparse(Lv L, Sp S, const T *xo, T *xn, const T *b, double w)
+{
+    const int n = S.nrows + S.nm;
+    for (int r = blockIdx.x * TPB + threadIdx.x; r < n; r += gridDim.x * TPB) {
+        if (r < S.nrows) {
+            const long long u = ghost_unknown(S, r);
+            const double xu = ld(xo, u);
+            const double ax = S.rsG[r] * (ghost_sum(S, xo, r) - xu);
+            st(xn, u, xu + w * (ld(b, u) - ax) / (-S.rsG[r]));
+        } else {
+            const int m = r - S.nrows;
+            const long long u = S.mslot[m];
+            const double xu = ld(xo, u);
+            double sd;
+            const double ax = mrow(L, S, xo, m, xu, sd);
+            st(xn, u, xu + w * (ld(b, u) - ax) / (-sd));
+        }
+    }
+}
+
 // membrane-adjacent cells of one colour (after the dense half-sweep): across
 // a cut link the neighbour's ghost unknown is eliminated, i.e. replaced by
 // the current value of its stencil, sum w x - b/sG

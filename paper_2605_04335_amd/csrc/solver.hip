@@ -111,6 +111,7 @@ struct poisson_ctx {
     double vol_fluid = 0.0, vol_pin = 0.0;
     int tail0 = 1;             // first level of the single-workgroup tail (FP32 levels in the mixed form)
     int tail0d = 1;            // the same for FP64 levels
+    std::vector<double> srj_w; // SRJ relaxation factors in application order
     DBuf<int32_t> rslot, rcol, mslot, mcol, mcolor;
     DBuf<double> rw, rsG, rdlb;
     std::vector<Level> lv;
@@ -385,6 +386,51 @@ void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
     for (int it = 0; it < o.nu2; ++it) fine_smooth<T>(c, x, b, sink, false, s);
 }
 
+// SRJ schedule: the reciprocals of the roots of the degree-m Chebyshev
+// polynomial on [kmin, 2], kmin = 16/m^2 (the minimax factors for the
+// amplification prod (1 - w k) over the spectrum of D^-1 A), in the order
+// smallest, largest, second smallest, ...
+std::vector<double> srj_schedule(int m)
+{
+    const double kmin = 16.0 / ((double)m * m), pi = 3.14159265358979323846;
+    std::vector<double> w(m), out;
+    for (int j = 1; j <= m; ++j)
+        w[j - 1] = 1.0 / (0.5 * (2.0 + kmin) - 0.5 * (2.0 - kmin) * std::cos(pi * (2 * j - 1) / (2.0 * m)));
+    std::sort(w.begin(), w.end());
+    for (int lo = 0, hi = m - 1; lo <= hi; ++lo, --hi) {
+        out.push_back(w[lo]);
+        if (hi != lo) out.push_back(w[hi]);
+    }
+    return out;
+}
+
+// x = SRJ(b): the scheduled sweeps from zero, alternating between x and the
+// residual scratch (the starting buffer is chosen so the last sweep lands in x)
+template <class T>
+void srj_apply(poisson_ctx &c, const T *b, T *x, hipStream_t s)
+{
+    T *tmp = std::is_same<T, double>::value ? (T *)c.rsp.p : (T *)c.frsp.p;
+    const Level &L = c.lv[0];
+    const int m = (int)c.srj_w.size(), nsp = (int)(c.nrows + c.nm);
+    T *xo = (m % 2) ? tmp : x, *xn = (m % 2) ? x : tmp;
+    k_fill<T><<<c.W0.nb, TPB, 0, s>>>(c.W0, xo, 0.0);
+    for (int q = 0; q < m; ++q) {
+        k0_jacobi<T><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, c.pin, xo, xn, b, c.srj_w[q]);
+        if (nsp) k0_jacobi_sparse<T><<<sparse_blocks(nsp), TPB, 0, s>>>(L.lv, c.sp, xo, xn, b, c.srj_w[q]);
+        std::swap(xo, xn);
+    }
+    IBM_LAUNCH_CHECK();
+}
+
+// x = M^-1 b: the V-cycle (with the pin sink) or SRJ; the output is not yet
+// shifted to a zero pin value (its consumers do that)
+template <class T>
+void precond(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
+{
+    if (c.opts.precond == IBM_PRECOND_SRJ) srj_apply<T>(c, b, x, s);
+    else vcycle<T>(c, b, x, sink, s);
+}
+
 // One BiCGSTAB iteration (van der Vorst 1992, right preconditioning): all
 // scalars stay on the device.
 template <class T, class TX>
@@ -394,14 +440,14 @@ void bicg_iteration(poisson_ctx &c, TX *y, T *r, T *rh, T *p, T *v, T *ph, T *sh
     const Lv &L = c.L0();
     k_p_update4<T><<<W.nb, TPB, 0, s>>>(L, W, c.Nt, r, p, v, c.sc.p, c.part.p);
     fin(c, W.nb, FIN_SINK, S_SINKP, 0.0, s);
-    vcycle<T>(c, p, ph, c.sc.p + S_SINKP, s);
+    precond<T>(c, p, ph, c.sc.p + S_SINKP, s);
     prof_begin(c, PK_APPLY0, s);
     int np = launch_apply<T>(c, M_PINZERO, false, 1, ph, v, nullptr, nullptr, rh, nullptr, s);
     prof_end(c, PK_APPLY0, s);
     fin(c, np, FIN_ALPHA, 0, 0.0, s);
     k_s_update4<T><<<W.nb, TPB, 0, s>>>(L, W, c.Nt, r, v, c.sc.p, c.part.p);
     fin(c, W.nb, FIN_SINK, S_SINKS, 0.0, s);
-    vcycle<T>(c, r, sh, c.sc.p + S_SINKS, s);
+    precond<T>(c, r, sh, c.sc.p + S_SINKS, s);
     np = launch_apply<T>(c, M_PINZERO, false, 2, sh, t, nullptr, nullptr, r, nullptr, s);
     fin(c, np, FIN_OMEGA, 0, 0.0, s);
     prof_begin(c, PK_XR, s);
@@ -570,7 +616,11 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
     poisson_opts &o = c->opts;
     IBM_REQUIRE(o.tol > 0 && o.max_iter > 0 && o.nu1 >= 1 && o.nu2 >= 0 && o.coarse_sweeps >= 1, IBM_EINVAL,
                 "bad solver options");
+    IBM_REQUIRE(o.precond == IBM_PRECOND_MG || (o.precond == IBM_PRECOND_SRJ && o.srj_sweeps >= 1 &&
+                                                 o.srj_sweeps <= IBM_SRJ_MAX_SWEEPS),
+                IBM_EINVAL, "bad preconditioner options");
     c->mixed = o.precision == IBM_PREC_MIXED;
+    if (o.precond == IBM_PRECOND_SRJ) c->srj_w = srj_schedule(o.srj_sweeps);
     c->g = read_grid(grid);
     for (int d = 0; d < 3; ++d) IBM_REQUIRE(c->g.n[d] == st->n[d], IBM_EINVAL, "stencil table of another grid");
     IBM_HIP(hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking));
@@ -912,6 +962,7 @@ int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
         read_scalars(c, s);
         const double bn2 = c.hsc[S_TMP2];
         double prev = HUGE_VAL;
+        bool inner_failed = false;
         for (outer = 0; outer <= o.max_outer; ++outer) {
             if (bn2 == 0.0) { rc = IBM_OK; rel = 0.0; break; }
             // r64 = b - A x (pinned) and its norm
@@ -922,23 +973,28 @@ int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
             rel = std::sqrt(c.hsc[S_TMP] / bn2);
             if (!std::isfinite(rel)) { rc = IBM_EBREAKDOWN; break; }
             if (rel <= o.tol) { rc = IBM_OK; break; }
-            if (rel > prev) {
-                // the FP32 correction made the FP64 residual larger: refinement
-                // has stalled (the FP32 solves cannot resolve this system: the
-                // condition number times the FP32 unit roundoff is not small).
-                // Undo the last correction and finish with an FP64 BiCGSTAB on
-                // the remaining residual.
-                k_add<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.d64.p, -1.0);
-                IBM_LAUNCH_CHECK();
+            if (rel > prev || inner_failed) {
+                // refinement has stalled: either the FP32 correction made the
+                // FP64 residual larger (the FP32 solves cannot resolve this
+                // system: the condition number times the FP32 unit roundoff is
+                // not small; that correction is undone), or the FP32 solve ran
+                // out of iterations before its tolerance.  Finish with an FP64
+                // BiCGSTAB on the remaining residual.
+                const bool grew = rel > prev;
+                if (grew) {
+                    k_add<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.d64.p, -1.0);
+                    IBM_LAUNCH_CHECK();
+                }
+                const double base = grew ? prev : rel;
                 if (log_enabled())
-                    fprintf(stderr, "[ibm] outer %d: rel %.3e > %.3e, refinement stalled: FP64 fallback\n", outer, rel,
-                            prev);
+                    fprintf(stderr, "[ibm] outer %d: rel %.3e (previous %.3e, inner %s), refinement stalled: FP64 fallback\n",
+                            outer, rel, prev, inner_failed ? "unconverged" : "converged");
                 ensure_fp64(c);
                 launch_apply<double>(c, M_PINNED, true, 2, c.x.p, c.r2.p, c.b.p, nullptr, c.b.p, nullptr, s);
                 int frc;
                 double frel;
                 its += bicgstab<double, double>(c, c.r2.p, c.d64.p, c.r.p, c.rh.p, c.p.p, c.v.p, c.ph.p, c.sh.p,
-                                                c.t.p, o.tol / prev, o.max_iter, true, &c.g64, s, &frc, &frel);
+                                                c.t.p, o.tol / base, o.max_iter, true, &c.g64, s, &frc, &frel);
                 k_add<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.d64.p);
                 int np = launch_apply<double>(c, M_PINNED, true, 2, c.x.p, c.r.p, c.b.p, nullptr, c.b.p, nullptr, s);
                 k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
@@ -965,6 +1021,7 @@ int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
                 fprintf(stderr, "[ibm] outer %d: rel %.3e, inner tol %.1e: %d iterations to %.2e (rc %d)\n", outer, rel,
                         itol, n_in, irel, irc);
             if (irc == IBM_EBREAKDOWN) { rc = irc; break; }
+            inner_failed = irc == IBM_ENOCONV;
             k_add<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.d64.p);
             IBM_LAUNCH_CHECK();
         }
@@ -996,6 +1053,8 @@ extern "C" void poisson_default_opts(poisson_opts *o)
     o->inner_tol = 1e-3;
     o->max_outer = 10;
     o->use_graph = 1;
+    o->precond = IBM_PRECOND_MG;
+    o->srj_sweeps = 16;
 }
 
 extern "C" int32_t poisson_workspace_estimate(int32_t nx, int32_t ny, int32_t nz, int64_t n_rows, int32_t precision,
@@ -1103,7 +1162,7 @@ extern "C" int32_t poisson_precond(poisson_ctx *c, const double *b_dev, double *
         to_split(*c, b_dev, c->r.p, c->nm, s);
         k_vsum<double, true><<<c->Wc.nb, TPB, 0, s>>>(c->L0(), c->Wc, c->r.p, c->part.p);
         fin(*c, c->Wc.nb, FIN_SINK, S_SINKP, 0.0, s);
-        vcycle<double>(*c, c->r.p, c->t.p, c->sc.p + S_SINKP, s);
+        precond<double>(*c, c->r.p, c->t.p, c->sc.p + S_SINKP, s);
         // shift: every active unknown minus the pin value, then the pin itself
         k_shift<double><<<c->W0.nb, TPB, 0, s>>>(c->L0(), c->W0, c->pin, c->t.p);
         k_shift_pin<<<1, 1, 0, s>>>(c->pin, c->t.p);

@@ -249,6 +249,10 @@ def test_error_paths(torch_cuda):
     f[5] = float("nan")
     x, stats = sol.solve(f, check=False)
     assert stats.status in (P.IBM_EBREAKDOWN, P.IBM_ENOCONV)
+    for m in (0, P.SRJ_MAX_SWEEPS + 1):
+        with pytest.raises(P.IbmError) as e:
+            P.Solver(p.xf, p.yf, p.zf, flags, st, precond="srj", srj_sweeps=m)
+        assert e.value.code == P.IBM_EINVAL
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -271,3 +275,68 @@ def test_caller_owned_workspace(torch_cuda, precision):
     x2, st2 = s2.solve(f)
     assert st2.iterations == st1.iterations
     assert torch.equal(x1, x2)
+
+
+# ---------------------------------------------------------------- SRJ preconditioner
+@pytest.mark.parametrize("name", ["c1", "membrane_64", "mixed_bodies_48", "box_odd"])
+def test_srj_precond_matches_oracle(torch_cuda, name):
+    torch = torch_cuda
+    p = CASES[name]
+    say("srj precond", name)
+    O = orc(name)
+    flags, st, sol, _ = gpu_setup(torch, p, precond="srj", srj_sweeps=16)
+    bo = oracle.assemble_rhs(p.xf, p.yf, p.zf, O.flags, O.st, p.f)
+    z = sol.precond(torch.from_numpy(bo).cuda()).cpu().numpy()
+    zo = oracle.srj(p.xf, p.yf, p.zf, O.flags, O.st, bo, oracle.srj_schedule(16), pinned=True, shift=True)
+    # independent schedules (each side computes the Chebyshev factors itself)
+    # and FMA contraction differ by rounding; the largest factor (~m^2/16)
+    # amplifies it over the 16 sweeps
+    assert rel(z, zo) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["c1", "membrane_64", "mixed_bodies_48"])
+def test_srj_solve_matches_oracle(torch_cuda, name):
+    torch = torch_cuda
+    p = CASES[name]
+    say("srj solve", name)
+    O = orc(name)
+    xo, bo, _, info = oracle.solve_problem(O, p.f, tol=1e-13, maxit=100)
+    # SRJ-BiCGSTAB converges smoothly (the V-cycle's iterations overshoot the
+    # tolerance by orders of magnitude), so the error sits near kappa * tol:
+    # 1e-12 gave 1.8e-10 on membrane_64; 1e-13 leaves room for the 1e-10 bound
+    flags, st, sol, _ = gpu_setup(torch, p, precond="srj", srj_sweeps=16, tol=1e-13, max_iter=1000)
+    x, stats = sol.solve(torch.from_numpy(p.f).cuda())
+    say("srj fp64: its %d residual %.2e vs oracle %.2e" % (stats.iterations, stats.rel_residual,
+                                                        rel(x.cpu().numpy(), xo)))
+    assert stats.status == 0 and stats.rel_residual <= 1e-13
+    assert rel(x.cpu().numpy(), xo) < 1e-10
+    # same for the mixed form: 1e-10 stopped at 4e-11 with a 1.9e-8 error
+    _, _, smx, _ = gpu_setup(torch, p, precond="srj", srj_sweeps=16, precision="mixed", tol=1e-12, max_iter=500,
+                             max_outer=20)
+    xm, sm = smx.solve(torch.from_numpy(p.f).cuda())
+    say("srj mixed: its %d outer %d residual %.2e vs oracle %.2e" % (sm.iterations, sm.outer_steps, sm.rel_residual,
+                                                                  rel(xm.cpu().numpy(), xo)))
+    assert sm.status == 0 and sm.rel_residual <= 1e-12
+    assert rel(xm.cpu().numpy(), xo) < 1e-8
+
+
+def test_mixed_inner_limit_falls_back_to_fp64(torch_cuda):
+    """An inner FP32 solve that stops at its iteration limit ends refinement:
+    the next outer step hands the remaining residual to one FP64 BiCGSTAB
+    (with the same limit) instead of starting another FP32 solve."""
+    import paper_2605_04335_amd as P
+    torch = torch_cuda
+    p = CASES["membrane_64"]
+    O = orc("membrane_64")
+    xo, bo, _, info = oracle.solve_problem(O, p.f, tol=1e-13, maxit=100)
+    # 5 SRJ-preconditioned iterations cannot reach the 1e-3 inner tolerance
+    # (the oracle's SRJ-BiCGSTAB needs 8 here), nor 1e-12 in FP64
+    _, _, smx, _ = gpu_setup(torch, p, precond="srj", srj_sweeps=16, precision="mixed", tol=1e-12, max_iter=5)
+    x, st = smx.solve(torch.from_numpy(p.f).cuda(), check=False)
+    say("inner limit: status %d its %d outer %d residual %.2e" % (st.status, st.iterations, st.outer_steps,
+                                                                 st.rel_residual))
+    assert st.status == P.IBM_ENOCONV and st.outer_steps == 1 and st.iterations == 10
+    _, _, smx, _ = gpu_setup(torch, p, precond="srj", srj_sweeps=16, precision="mixed", tol=1e-12, max_iter=200)
+    x, st = smx.solve(torch.from_numpy(p.f).cuda())
+    assert st.status == 0 and st.rel_residual <= 1e-12
+    assert rel(x.cpu().numpy(), xo) < 1e-8
