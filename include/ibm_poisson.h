@@ -216,6 +216,47 @@ int32_t poisson_workspace_estimate(int32_t nx, int32_t ny, int32_t nz, int64_t n
 int32_t poisson_solve(poisson_ctx *ctx, const double *f_dev, const double *g_dev, double *x_dev,
                       poisson_stats *stats, void *stream);
 
+/*
+ * Moving bodies (the paper's time loop, Sec. 2.4 and 2.5: every step
+ * re-classifies the grid and rebuilds the ghost rows before the PPE).
+ *
+ * poisson_update -- re-set-up of a context after the bodies moved: the same
+ * grid and options, a new classification (flags_dev, device uint8[N]) and
+ * ghost-row table.  Every part of the context that depends on them (level-0
+ * flags, ghost and membrane rows, pin, volumes, coarse masks of every level)
+ * is rebuilt on the device; the level geometry, prolongation maps and coarse
+ * storage are kept.  The vectors over the unknowns are reallocated only
+ * when the new membrane ghost count needs more than they hold (with headroom
+ * for later steps); such a reallocation moves them out of a caller-bound
+ * workspace.  The results equal those of a fresh poisson_setup bit for bit.
+ * Synchronous.  IBM_EINVAL for a table of another grid, IBM_EGEOM for a
+ * classification without fluid or a cut link without a ghost row,
+ * IBM_ENOMEM; after an error the context may only be destroyed.
+ *
+ * poisson_solve_from -- poisson_solve from an initial guess x0_dev (device
+ * double[n_x0], natural order), e.g. the previous step's pressure after
+ * ibm_fill_fresh.  n_x0 = N: cell values only; each membrane ghost unknown
+ * (the other side's field at its cell) then starts from the mean of the
+ * cells across its cell's cut links.  n_x0 = N + n_mghost: cell values and
+ * membrane ghost values (a solution of this geometry).  Solid non-ghost
+ * cells start from zero and the guess is shifted to a zero pin value; FP64
+ * contexts then solve for the correction, mixed ones start the refinement
+ * from it.  x0_dev and x_dev (double[N+n_mghost]) must not overlap.  Same
+ * returns as poisson_solve, and IBM_EINVAL for another n_x0.
+ *
+ * ibm_fill_fresh -- initial values of fresh cells, cells that are fluid
+ * under flags_new and were solid under flags_old: each gets the mean of its
+ * face neighbours that are fluid under both (summed in the order -x, +x, -y,
+ * +y, -z, +z), and keeps its value when there is none.  x_dev: device
+ * double[N], natural order, updated in place; *n_fresh (may be NULL)
+ * receives the fresh-cell count.  Synchronous with stream.
+ */
+int32_t poisson_update(poisson_ctx *ctx, const uint8_t *flags_dev, const ibm_stencils *st);
+int32_t poisson_solve_from(poisson_ctx *ctx, const double *f_dev, const double *g_dev, const double *x0_dev,
+                           int64_t n_x0, double *x_dev, poisson_stats *stats, void *stream);
+int32_t ibm_fill_fresh(const ibm_grid *grid, const uint8_t *flags_old_dev, const uint8_t *flags_new_dev,
+                       double *x_dev, int64_t *n_fresh, void *stream);
+
 /* y = A x with the pinned operator (device double[N+n_mghost] each). */
 int32_t poisson_apply(poisson_ctx *ctx, const double *x_dev, double *y_dev, void *stream);
 

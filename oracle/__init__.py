@@ -18,7 +18,7 @@ import ctypes
 import os
 import subprocess
 from dataclasses import dataclass
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -305,3 +305,31 @@ def solve_problem(S: Setup, f, tol=1e-13, maxit=300, g=None):
 def threads() -> int:
     """OpenMP threads the oracle uses."""
     return int(lib().orc_threads())
+
+
+def fill_fresh(nx, ny, nz, flags_old, flags_new, x) -> Tuple[np.ndarray, int]:
+    """Initial values of fresh cells for a moving-body step (the time loop of
+    Sec. 2.4 re-classifies the grid every step): a cell that is fluid under
+    flags_new and was solid under flags_old has no pressure history and takes
+    the mean of its face neighbours that are fluid under both, added in the
+    order -x, +x, -y, +y, -z, +z; with no such neighbour it keeps its value.
+    Returns (new x, fresh-cell count); a plain loop over the fresh cells."""
+    fo = np.asarray(flags_old, dtype=np.uint8)
+    fn = np.asarray(flags_new, dtype=np.uint8)
+    out = np.array(x, dtype=np.float64, copy=True)
+    fresh = np.nonzero(((fn & F_SOLID) == 0) & ((fo & F_SOLID) != 0))[0]
+    fluid_both = ((fn & F_SOLID) == 0) & ((fo & F_SOLID) == 0)
+    for p in fresh:
+        p = int(p)
+        i, j, k = p % nx, (p // nx) % ny, p // (nx * ny)
+        acc, cnt = 0.0, 0
+        for (d, n_d, c_d, stride) in ((0, nx, i, 1), (1, ny, j, nx), (2, nz, k, nx * ny)):
+            for sg in (-1, 1):
+                if 0 <= c_d + sg < n_d:
+                    q = p + sg * stride
+                    if fluid_both[q]:
+                        acc += float(x[q])
+                        cnt += 1
+        if cnt:
+            out[p] = acc / cnt
+    return out, len(fresh)

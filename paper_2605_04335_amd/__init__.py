@@ -85,7 +85,8 @@ EXPORTS = ["ibm_classify", "ibm_build_ghost_stencils", "ibm_stencils_info", "ibm
            "ibm_stencils_free", "poisson_default_opts", "poisson_setup", "poisson_workspace_estimate",
            "poisson_solve", "poisson_apply", "poisson_assemble_rhs", "poisson_precond", "poisson_solve_assembled",
            "poisson_destroy", "poisson_workspace_size", "poisson_bind_workspace", "poisson_server_create",
-           "poisson_submit", "poisson_poll", "poisson_server_drain", "poisson_server_destroy", "ibm_last_error"]
+           "poisson_submit", "poisson_poll", "poisson_server_drain", "poisson_server_destroy", "ibm_last_error",
+           "poisson_update", "poisson_solve_from", "ibm_fill_fresh"]
 
 _lib = None
 
@@ -177,6 +178,17 @@ def classify(xf, yf, zf, bodies, device="cuda"):
     return flags, {k: getattr(st, k) for k, _ in st._fields_}
 
 
+def fill_fresh(xf, yf, zf, flags_old, flags_new, x) -> int:
+    """Fresh cells (fluid now, solid before) take the mean of their neighbours
+    that are fluid at both steps; x (device double[N]) in place.  Returns the
+    fresh-cell count."""
+    G = _GridArgs(xf, yf, zf)
+    n = ctypes.c_int64()
+    _check(lib().ibm_fill_fresh(ctypes.byref(G.g), _tptr(flags_old), _tptr(flags_new), _tptr(x), ctypes.byref(n),
+                                _stream()), "ibm_fill_fresh")
+    return n.value
+
+
 class Stencils:
     def __init__(self, handle, N):
         self.h = handle
@@ -256,6 +268,27 @@ class Solver:
         if check:
             _check(rc, "poisson_solve")
         return x, st
+
+    def solve_from(self, f, x0, g=None, x=None, check=True):
+        """Solve from an initial guess x0 (device double[N] cell values, or
+        double[N + n_mghost] with the membrane ghost values)."""
+        import torch
+        assert f.dtype == torch.float64 and f.is_cuda and f.is_contiguous() and f.numel() == self.N
+        assert x0.dtype == torch.float64 and x0.is_cuda and x0.is_contiguous()
+        if x is None:
+            x = self._vec(f.device)
+        st = PoissonStats()
+        rc = lib().poisson_solve_from(self.h, _tptr(f), _tptr(g) if g is not None else None, _tptr(x0),
+                                      ctypes.c_int64(x0.numel()), _tptr(x), ctypes.byref(st), _stream())
+        if check:
+            _check(rc, "poisson_solve_from")
+        return x, st
+
+    def update(self, flags, stencils: "Stencils"):
+        """Re-set-up for moved bodies: same grid and options, new flags and ghost rows."""
+        _check(lib().poisson_update(self.h, _tptr(flags), stencils.h), "poisson_update")
+        ng, nm, nf = stencils.info()
+        self.nm, self.ng = nm, ng
 
     def solve_assembled(self, b, x=None, check=True):
         if x is None:

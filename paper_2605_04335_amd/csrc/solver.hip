@@ -15,6 +15,7 @@
 // ABI takes and returns natural x-fastest arrays, converted at the boundary.
 
 #include "kernels.hpp"
+#include "setup.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -50,7 +51,6 @@ struct Level {
     Lv lv;
     PMap pm;
     std::vector<double> hc[3], hw[3];
-    std::vector<uint8_t> hm;         // natural-layout host mask during setup
 };
 
 void level_geometry(Level &L, const std::vector<double> *f, hipStream_t s)
@@ -127,10 +127,14 @@ struct poisson_ctx {
     DBuf<double> d64;
     DBuf<double> r2;           // mixed: right-hand side of the FP64 fallback solve
     DBuf<double> gtmp, sc, part;
+    DBuf<double> ssum;          // set-up sums (fluid volume, active volume per level)
+    DBuf<int> serr;             // set-up error flag
+    DBuf<uint8_t> hact[2];      // set-up: natural-order coarse active/cut bits of two consecutive levels
     double *hsc = nullptr;
     hipStream_t cs = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr, ej = nullptr;
     hipGraphExec_t g64 = nullptr, g32 = nullptr;
+    hipGraphExec_t g64w = nullptr;  // FP64 iteration on the correction (solves from a guess)
     size_t bytes = 0;
     bool mixed = false;
     // per-launch timing of one kernel (HIP events on the solve stream)
@@ -147,6 +151,7 @@ struct poisson_ctx {
     {
         if (g64) (void)hipGraphExecDestroy(g64);
         if (g32) (void)hipGraphExecDestroy(g32);
+        if (g64w) (void)hipGraphExecDestroy(g64w);
         if (hsc) (void)hipHostFree(hsc);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
@@ -608,6 +613,126 @@ size_t estimate_bytes(int nx, int ny, int nz, long long nrows, int precision)
     return b;
 }
 
+// grow-only device buffer: reallocated (contents dropped) when too small
+template <class T>
+void reserve(DBuf<T> &b, size_t n)
+{
+    if (!b.p || b.n < n) b.alloc(n);
+}
+
+// Flag-dependent parts of a context -- level-0 flags, ghost and membrane rows
+// in slot numbering, fluid and pin volumes, coarse masks, vectors sized by
+// the unknown count -- built on the device from the classification and the
+// ghost-row table.  Runs at set-up and again when bodies move.
+void setup_geometry(poisson_ctx &c, const uint8_t *flags, const ibm_stencils *st)
+{
+    const HostGrid &g = c.g;
+    for (int d = 0; d < 3; ++d) IBM_REQUIRE(g.n[d] == st->n[d], IBM_EINVAL, "stencil table of another grid");
+    IBM_REQUIRE(st->pin >= 0 && st->pin < c.N, IBM_EGEOM, "no fluid cell to pin");
+    hipStream_t s = c.cs;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int nl = (int)c.lv.size();
+    Level &Z = c.lv[0];
+    c.ng = st->ng;
+    c.nm = st->nm;
+    c.nrows = st->ng + st->nm;
+    c.n_fallback = st->nfallback;
+    const long long R = c.nrows, nm = c.nm, N = c.N;
+    const SlotMap sm{nx, ny, Z.H, Z.Nh, N, c.N2};
+    {
+        const long long p = st->pin;
+        const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((long long)nx * ny));
+        c.pin = host_slot(Z.H, ny, Z.Nh, i, j, k);
+        c.vol_pin = Z.hw[0][i] * Z.hw[1][j] * Z.hw[2][k];
+    }
+    // the captured iterations and the vectors below may change
+    IBM_HIP(hipStreamSynchronize(s));
+    if (c.g64) { (void)hipGraphExecDestroy(c.g64); c.g64 = nullptr; }
+    if (c.g32) { (void)hipGraphExecDestroy(c.g32); c.g32 = nullptr; }
+    if (c.g64w) { (void)hipGraphExecDestroy(c.g64w); c.g64w = nullptr; }
+    k_setup_flags0<<<Z.walk.nb, TPB, 0, s>>>(Z.lv, Z.walk, flags, Z.m.p);
+    // ghost and membrane rows
+    const long long R1 = std::max<long long>(R, 1), M1 = std::max<long long>(nm, 1);
+    reserve(c.rslot, std::max<long long>(c.ng, 1));
+    reserve(c.rcol, R1 * 8);
+    reserve(c.rw, R1 * 8);
+    reserve(c.rsG, R1);
+    reserve(c.rdlb, R1);
+    reserve(c.gtmp, R1);
+    reserve(c.mslot, M1);
+    reserve(c.mcol, M1 * 6);
+    reserve(c.mcolor, M1);
+    auto blocks = [](long long n) { return (int)std::min<long long>(std::max<long long>((n + TPB - 1) / TPB, 1), 4096); };
+    if (R) {
+        k_setup_rows<<<blocks(8 * R), TPB, 0, s>>>(sm, c.ng, R, st->cell.p, st->col.p, c.rslot.p, c.rcol.p);
+        IBM_HIP(hipMemcpyAsync(c.rw.p, st->w.p, R * 64, hipMemcpyDeviceToDevice, s));
+        IBM_HIP(hipMemcpyAsync(c.rsG.p, st->sG.p, R * 8, hipMemcpyDeviceToDevice, s));
+        IBM_HIP(hipMemcpyAsync(c.rdlb.p, st->dlb.p, R * 8, hipMemcpyDeviceToDevice, s));
+    }
+    IBM_HIP(hipMemsetAsync(c.serr.p, 0, sizeof(int), s));
+    if (nm)
+        k_setup_membrane<<<blocks(nm), TPB, 0, s>>>(sm, nz, nm, st->cell.p + c.ng, flags, c.mslot.p, c.mcol.p,
+                                                    c.mcolor.p, c.serr.p);
+    // fluid volume, then the coarse masks level by level with their active volumes
+    k_fluid_volume<<<Z.walk.nb, TPB, 0, s>>>(Z.lv, Z.walk, c.part.p);
+    k_fin<<<1, 1024, 0, s>>>(c.part.p, PSTRIDE, Z.walk.nb, FIN_SUM, 0, 0.0, c.ssum.p);
+    for (int l = 1; l < nl; ++l) {
+        Level &F = c.lv[l - 1], &C = c.lv[l];
+        const uint8_t *fine = l == 1 ? flags : c.hact[l & 1].p;
+        uint8_t *ha = c.hact[(l + 1) & 1].p;
+        k_coarse_active<<<blocks(C.N), TPB, 0, s>>>(F.n[0], F.n[1], C.n[0], C.n[1], C.N, fine, l == 1, ha);
+        k_coarse_mask<<<C.walk.nb, TPB, 0, s>>>(C.lv, C.walk, ha, C.m.p, c.part.p);
+        k_fin<<<1, 1024, 0, s>>>(c.part.p, PSTRIDE, C.walk.nb, FIN_SUM, l, 0.0, c.ssum.p);
+    }
+    IBM_LAUNCH_CHECK();
+    double hs[32];
+    int herr = 0;
+    IBM_HIP(hipMemcpyAsync(hs, c.ssum.p, nl * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipMemcpyAsync(&herr, c.serr.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    IBM_REQUIRE(herr == 0, IBM_EGEOM, "cut link without ghost");
+    c.vol_fluid = hs[0];
+    for (int l = 1; l < nl; ++l) c.lv[l].volA = hs[l];
+    Sp &S = c.sp;
+    S.N2 = c.N2;
+    S.pin = c.pin;
+    S.nrows = (int)R;
+    S.ng = (int)c.ng;
+    S.rslot = c.rslot.p; S.rcol = c.rcol.p; S.rw = c.rw.p; S.rsG = c.rsG.p;
+    S.nm = (int)nm;
+    S.mslot = c.mslot.p; S.mcol = c.mcol.p; S.mcolor = c.mcolor.p;
+    // vectors over the unknowns: exact size at set-up; when an update needs
+    // more, every held vector is reallocated with headroom for later updates
+    const long long Nt = c.N2 + nm;
+    const bool first = !c.x.p;
+    c.Nt = Nt;
+    c.W0 = make_walk(Nt);
+    c.W4 = make_walk((Nt + 3) / 4);
+    const long long cap = first ? Nt : Nt + nm / 4 + 1024;
+    DBuf<double> *dv[] = {&c.x, &c.r, &c.b, &c.t, &c.rh, &c.p, &c.v, &c.ph, &c.sh, &c.rsp, &c.d64, &c.r2};
+    DBuf<float> *fv[] = {&c.fr, &c.frh, &c.fp, &c.fv, &c.fph, &c.fsh, &c.ft, &c.frsp};
+    if (first) {
+        c.x.alloc(Nt); c.r.alloc(Nt); c.b.alloc(Nt); c.t.alloc(Nt);
+        if (!c.mixed) {
+            c.rh.alloc(Nt); c.p.alloc(Nt); c.v.alloc(Nt); c.ph.alloc(Nt); c.sh.alloc(Nt); c.rsp.alloc(Nt);
+        } else {
+            c.d64.alloc(Nt); c.fr.alloc(Nt); c.frh.alloc(Nt); c.fp.alloc(Nt); c.fv.alloc(Nt);
+            c.fph.alloc(Nt); c.fsh.alloc(Nt); c.ft.alloc(Nt); c.frsp.alloc(Nt);
+        }
+    } else {
+        for (auto *q : dv)
+            if (q->p && (long long)q->n < Nt) q->alloc(cap);
+        for (auto *q : fv)
+            if (q->p && (long long)q->n < Nt) q->alloc(cap);
+    }
+    std::vector<double> sc0(S_COUNT, 0.0);
+    sc0[S_VPIN] = c.vol_pin;
+    IBM_HIP(hipMemcpyAsync(c.sc.p, sc0.data(), S_COUNT * 8, hipMemcpyHostToDevice, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    c.bytes = estimate_bytes(nx, ny, nz, c.nrows, c.opts.precision);
+    IBM_REQUIRE(c.W0.nb <= PSTRIDE - 2048, IBM_EINVAL, "grid too large");
+}
+
 poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencils *st, const poisson_opts *opts)
 {
     IBM_REQUIRE(flags && st, IBM_EINVAL, "null argument");
@@ -631,23 +756,8 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
     hipStream_t s = c->cs;
     const HostGrid &g = c->g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const long long N = (long long)nx * ny * nz;
-    c->N = N;
-    c->ng = st->ng;
-    c->nm = st->nm;
-    c->nrows = st->ng + st->nm;
-    c->n_fallback = st->nfallback;
-    // host copies of the classification and the ghost rows
-    std::vector<uint8_t> hf(N);
-    IBM_HIP(hipMemcpyAsync(hf.data(), flags, N, hipMemcpyDeviceToHost, s));
-    const long long R = c->nrows;
-    std::vector<int32_t> hcell(std::max<long long>(R, 1)), hcol(std::max<long long>(R, 1) * 8);
-    if (R) {
-        IBM_HIP(hipMemcpyAsync(hcell.data(), st->cell.p, R * 4, hipMemcpyDeviceToHost, s));
-        IBM_HIP(hipMemcpyAsync(hcol.data(), st->col.p, R * 32, hipMemcpyDeviceToHost, s));
-    }
-    IBM_HIP(hipStreamSynchronize(s));
-    // levels
+    c->N = (long long)nx * ny * nz;
+    // levels: halve while every dimension is even and the smallest exceeds 4
     int nl = 1;
     {
         int n[3] = {nx, ny, nz};
@@ -675,140 +785,10 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
     }
     // level 0: shorter plane runs per thread (more tiles) measured faster
     c->lv[0].geo = make_geo(c->lv[0].H, c->lv[0].n[1], c->lv[0].n[2], 16384);
-    Level &Z = c->lv[0];
-    c->N2 = 2 * Z.Nh;
-    c->Nt = c->N2 + c->nm;
-    auto slot0 = [&](long long cell) {
-        int i = (int)(cell % nx), j = (int)((cell / nx) % ny), k = (int)(cell / ((long long)nx * ny));
-        return host_slot(Z.H, ny, Z.Nh, i, j, k);
-    };
-    auto unk0 = [&](long long col) { return col < N ? slot0(col) : c->N2 + (col - N); };
-    // level-0 flags in split layout (padding slots are solid)
-    {
-        std::vector<uint8_t> sf(c->N2, F_SOLID);
-        for (int k = 0; k < nz; ++k)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i)
-                    sf[host_slot(Z.H, ny, Z.Nh, i, j, k)] = hf[i + (long long)nx * (j + (long long)ny * k)];
-        upload(Z.m, sf, s);
-    }
-    c->pin = slot0(st->pin);
-    // sparse rows
-    {
-        std::vector<int32_t> rs(std::max<long long>(c->ng, 1)), rc(std::max<long long>(R, 1) * 8, -1);
-        for (long long r = 0; r < c->ng; ++r) rs[r] = (int32_t)slot0(hcell[r]);
-        for (long long q = 0; q < R * 8; ++q) rc[q] = hcol[q] >= 0 ? (int32_t)unk0(hcol[q]) : -1;
-        upload(c->rslot, rs, s);
-        upload(c->rcol, rc, s);
-        const long long RR = std::max<long long>(R, 1);
-        c->rw.alloc(RR * 8); c->rsG.alloc(RR); c->rdlb.alloc(RR);
-        if (R) {
-            IBM_HIP(hipMemcpyAsync(c->rw.p, st->w.p, R * 64, hipMemcpyDeviceToDevice, s));
-            IBM_HIP(hipMemcpyAsync(c->rsG.p, st->sG.p, R * 8, hipMemcpyDeviceToDevice, s));
-            IBM_HIP(hipMemcpyAsync(c->rdlb.p, st->dlb.p, R * 8, hipMemcpyDeviceToDevice, s));
-        }
-        // membrane-adjacent cells: slots, colours, and neighbour unknowns (-x,+x,-y,+y,-z,+z)
-        const long long nm = c->nm;
-        std::vector<int32_t> ms(std::max<long long>(nm, 1)), mc(std::max<long long>(nm, 1) * 6, -1),
-            mk(std::max<long long>(nm, 1));
-        std::vector<int32_t> mcell(hcell.begin() + c->ng, hcell.begin() + c->ng + nm);
-        for (long long m = 0; m < nm; ++m) {
-            long long p = mcell[m];
-            int ci[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / ((long long)nx * ny))};
-            long long strd[3] = {1, nx, (long long)nx * ny};
-            ms[m] = (int32_t)slot0(p);
-            mk[m] = (ci[0] + ci[1] + ci[2]) & 1;
-            for (int d = 0; d < 3; ++d)
-                for (int sg = 0; sg < 2; ++sg) {
-                    int c2 = ci[d] + (sg ? 1 : -1);
-                    if (c2 < 0 || c2 >= g.n[d]) continue;
-                    long long q = p + (sg ? strd[d] : -strd[d]);
-                    long long lo = sg ? p : q;
-                    long long col;
-                    if (hf[lo] & (F_CUTX << d)) {
-                        auto it = std::lower_bound(mcell.begin(), mcell.end(), (int32_t)q);
-                        IBM_REQUIRE(it != mcell.end() && *it == q, IBM_EGEOM, "cut link without ghost");
-                        col = c->N2 + (it - mcell.begin());
-                    } else {
-                        col = slot0(q);
-                    }
-                    mc[6 * m + 2 * d + sg] = (int32_t)col;
-                }
-        }
-        upload(c->mslot, ms, s);
-        upload(c->mcol, mc, s);
-        upload(c->mcolor, mk, s);
-    }
-    // fluid volume, pin volume
-    {
-        double sv = 0.0;
-        for (int k = 0; k < nz; ++k)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i)
-                    if (!(hf[i + (long long)nx * (j + (long long)ny * k)] & F_SOLID))
-                        sv += Z.hw[0][i] * Z.hw[1][j] * Z.hw[2][k];
-        c->vol_fluid = sv;
-        long long p = st->pin;
-        int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((long long)nx * ny));
-        c->vol_pin = Z.hw[0][i] * Z.hw[1][j] * Z.hw[2][k];
-    }
-    // coarse masks: active, cut (propagated), open faces; then split layout
+    c->N2 = 2 * c->lv[0].Nh;
+    // prolongation maps of each level from its coarse parent
     for (int l = 1; l < nl; ++l) {
         Level &F = c->lv[l - 1], &C = c->lv[l];
-        C.hm.assign(C.N, 0);
-        const int fnx = F.n[0], fny = F.n[1];
-        for (int K = 0; K < C.n[2]; ++K)
-            for (int J = 0; J < C.n[1]; ++J)
-                for (int I = 0; I < C.n[0]; ++I) {
-                    uint8_t act = 0, cut = 0;
-                    for (int q = 0; q < 8; ++q) {
-                        int dx = q & 1, dy = (q >> 1) & 1, dz = (q >> 2) & 1;
-                        long long p = (2 * I + dx) + (long long)fnx * ((2 * J + dy) + (long long)fny * (2 * K + dz));
-                        uint8_t a, cb;
-                        if (l == 1) {
-                            uint8_t f = hf[p];
-                            a = (!(f & F_SOLID) || (f & F_GHOST)) ? 1 : 0;
-                            cb = (f >> 4) & 7;
-                        } else {
-                            a = F.hm[p] & 1;
-                            cb = (F.hm[p] >> 4) & 7;
-                        }
-                        act |= a;
-                        if (dx && (cb & 1)) cut |= 16;
-                        if (dy && (cb & 2)) cut |= 32;
-                        if (dz && (cb & 4)) cut |= 64;
-                    }
-                    C.hm[I + (long long)C.n[0] * (J + (long long)C.n[1] * K)] = act | cut;
-                }
-        double va = 0.0;
-        for (int K = 0; K < C.n[2]; ++K)
-            for (int J = 0; J < C.n[1]; ++J)
-                for (int I = 0; I < C.n[0]; ++I) {
-                    long long P = I + (long long)C.n[0] * (J + (long long)C.n[1] * K);
-                    if (!(C.hm[P] & 1)) continue;
-                    va += C.hw[0][I] * C.hw[1][J] * C.hw[2][K];
-                    long long strd[3] = {1, C.n[0], (long long)C.n[0] * C.n[1]};
-                    int ci[3] = {I, J, K};
-                    for (int d = 0; d < 3; ++d)
-                        if (ci[d] + 1 < C.n[d] && (C.hm[P + strd[d]] & 1) && !(C.hm[P] & (16 << d)))
-                            C.hm[P] |= (uint8_t)(2 << d);
-                }
-        C.volA = va;
-        // device mask: active and +faces from hm, -faces copied from the
-        // neighbour's +face bit (hm keeps the cut bits for the next level)
-        std::vector<uint8_t> sm(2 * C.Nh, 0);
-        for (int K = 0; K < C.n[2]; ++K)
-            for (int J = 0; J < C.n[1]; ++J)
-                for (int I = 0; I < C.n[0]; ++I) {
-                    const long long P = I + (long long)C.n[0] * (J + (long long)C.n[1] * K);
-                    uint8_t m = C.hm[P] & 15;
-                    if (I > 0 && (C.hm[P - 1] & 2)) m |= 16;
-                    if (J > 0 && (C.hm[P - C.n[0]] & 4)) m |= 32;
-                    if (K > 0 && (C.hm[P - (long long)C.n[0] * C.n[1]] & 8)) m |= 64;
-                    sm[host_slot(C.H, C.n[1], C.Nh, I, J, K)] = m;
-                }
-        upload(C.m, sm, s);
-        // prolongation maps of F from C
         for (int d = 0; d < 3; ++d) {
             int nf = F.n[d], nc = C.n[d];
             std::vector<int> pi(nf);
@@ -825,7 +805,7 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
             upload(F.pt[d], pt, s);
         }
     }
-    // device views, coarse storage, tail start
+    // tail start (the coarsest levels that fit one workgroup's LDS)
     for (int pass = 0; pass < 2; ++pass) {
         const size_t tsz = pass ? sizeof(double) : sizeof(float);
         int &t0 = pass ? c->tail0d : c->tail0;
@@ -840,8 +820,10 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
         }
     }
     if (!c->mixed) c->tail0 = c->tail0d;
+    // device views, masks and coarse storage
     for (int l = 0; l < nl; ++l) {
         Level &L = c->lv[l];
+        L.m.alloc(2 * L.Nh);
         Lv &v = L.lv;
         v.nx = L.n[0]; v.ny = L.n[1]; v.nz = L.n[2]; v.H = L.H; v.Nh = L.Nh;
         v.fH = make_fdiv(L.H);
@@ -854,36 +836,18 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
             else { L.x64.alloc(2 * L.Nh); L.b64.alloc(2 * L.Nh); }
         }
     }
-    Sp &S = c->sp;
-    S.N2 = c->N2;
-    S.pin = c->pin;
-    S.nrows = (int)c->nrows;
-    S.ng = (int)c->ng;
-    S.rslot = c->rslot.p; S.rcol = c->rcol.p; S.rw = c->rw.p; S.rsG = c->rsG.p;
-    S.nm = (int)c->nm;
-    S.mslot = c->mslot.p; S.mcol = c->mcol.p; S.mcolor = c->mcolor.p;
-    c->W0 = make_walk(c->Nt);
-    c->W4 = make_walk((c->Nt + 3) / 4);
+    IBM_REQUIRE(c->lv[0].geo.nb <= PSTRIDE - 2048, IBM_EINVAL, "grid too large");
+    for (auto &L : c->lv) IBM_REQUIRE(L.geo.nb <= PSTRIDE && L.geon.nb <= PSTRIDE, IBM_EINVAL, "grid too large");
     c->Wc = make_walk(c->N2);
-    const long long Nt = c->Nt;
-    c->x.alloc(Nt); c->r.alloc(Nt); c->b.alloc(Nt); c->t.alloc(Nt);
-    if (!c->mixed) {
-        c->rh.alloc(Nt); c->p.alloc(Nt); c->v.alloc(Nt); c->ph.alloc(Nt); c->sh.alloc(Nt); c->rsp.alloc(Nt);
-    } else {
-        c->d64.alloc(Nt); c->fr.alloc(Nt); c->frh.alloc(Nt); c->fp.alloc(Nt); c->fv.alloc(Nt);
-        c->fph.alloc(Nt); c->fsh.alloc(Nt); c->ft.alloc(Nt); c->frsp.alloc(Nt);
-    }
-    c->gtmp.alloc(std::max<long long>(R, 1));
     c->sc.alloc(S_COUNT);
     c->part.alloc((size_t)PSTRIDE * 4);
-    std::vector<double> sc0(S_COUNT, 0.0);
-    sc0[S_VPIN] = c->vol_pin;
-    IBM_HIP(hipMemcpyAsync(c->sc.p, sc0.data(), S_COUNT * 8, hipMemcpyHostToDevice, s));
-    IBM_HIP(hipStreamSynchronize(s));
-    c->bytes = estimate_bytes(nx, ny, nz, c->nrows, o.precision);
-    for (auto &L : c->lv) { L.hm.clear(); L.hm.shrink_to_fit(); }
-    IBM_REQUIRE(c->lv[0].geo.nb <= PSTRIDE - 2048 && c->W0.nb <= PSTRIDE - 2048, IBM_EINVAL, "grid too large");
-    for (auto &L : c->lv) IBM_REQUIRE(L.geo.nb <= PSTRIDE && L.geon.nb <= PSTRIDE, IBM_EINVAL, "grid too large");
+    c->ssum.alloc(32);
+    c->serr.alloc(1);
+    if (nl > 1) {
+        c->hact[0].alloc(c->lv[1].N);
+        if (nl > 2) c->hact[1].alloc(c->lv[2].N);
+    }
+    setup_geometry(*c, flags, st);
     return c.release();
 }
 
@@ -928,7 +892,6 @@ void assemble_rhs(poisson_ctx &c, const double *f, const double *gval, double *b
     IBM_LAUNCH_CHECK();
 }
 
-// solve A x = b (assembled, in c.b, split) into c.x; returns status
 // FP64 storage of a mixed context, allocated on first need: the coarse FP64
 // levels and the FP64 Krylov vectors (the FP64 cycle uses its own tail start)
 void ensure_fp64(poisson_ctx &c)
@@ -943,19 +906,53 @@ void ensure_fp64(poisson_ctx &c)
         if (!b->p) b->alloc(c.Nt);
 }
 
-int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
+// solve A x = b (assembled, in c.b, split) into c.x; returns status.  warm:
+// c.x holds an initial guess (zero on inactive slots, zero at the pin)
+int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s, bool warm = false)
 {
     const poisson_opts &o = c.opts;
     int rc = IBM_ENOCONV, its = 0, outer = 0;
     double rel = 1.0;
-    if (!c.mixed) {
+    if (!c.mixed && !warm) {
         its = bicgstab<double, double>(c, c.b.p, c.x.p, c.r.p, c.rh.p, c.p.p, c.v.p, c.ph.p, c.sh.p, c.t.p, o.tol, o.max_iter,
                                true, &c.g64, s, &rc, &rel);
         if (log_enabled()) fprintf(stderr, "[ibm] fp64: %d iterations to %.3e (rc %d)\n", its, rel, rc);
+    } else if (!c.mixed) {
+        // FP64 from an initial guess: BiCGSTAB on the correction, A d = b - A x0
+        const Walk &W = c.W0;
+        reserve(c.d64, c.Nt);
+        reserve(c.r2, c.Nt);
+        k_dot2<double><<<W.nb, TPB, 0, s>>>(W, c.b.p, c.b.p, c.part.p, PSTRIDE);
+        k_fin<<<1, 1024, 0, s>>>(c.part.p, PSTRIDE, W.nb, FIN_SUM, S_TMP2, 0.0, c.sc.p);
+        int np = launch_apply<double>(c, M_PINNED, true, 2, c.x.p, c.r2.p, c.b.p, nullptr, c.b.p, nullptr, s);
+        k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
+        IBM_LAUNCH_CHECK();
+        read_scalars(c, s);
+        const double bn2 = c.hsc[S_TMP2];
+        const double rel0 = bn2 > 0.0 ? std::sqrt(c.hsc[S_TMP] / bn2) : 0.0;
+        if (!std::isfinite(rel0)) {
+            rc = IBM_EBREAKDOWN;
+        } else if (bn2 == 0.0) {
+            k_fill<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, 0.0);
+            rc = IBM_OK;
+            rel = 0.0;
+        } else if (rel0 <= o.tol) {
+            rc = IBM_OK;
+            rel = rel0;
+        } else {
+            double r1;
+            its = bicgstab<double, double>(c, c.r2.p, c.d64.p, c.r.p, c.rh.p, c.p.p, c.v.p, c.ph.p, c.sh.p, c.t.p,
+                                           o.tol / rel0, o.max_iter, true, &c.g64w, s, &rc, &r1);
+            k_add<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, c.d64.p);
+            IBM_LAUNCH_CHECK();
+            rel = r1 * rel0;
+        }
+        if (log_enabled())
+            fprintf(stderr, "[ibm] fp64 from a guess (rel %.3e): %d iterations to %.3e (rc %d)\n", rel0, its, rel, rc);
     } else {
         // FP64 iterative refinement around FP32 inner solves
         const Walk &W = c.W0;
-        k_fill<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, 0.0);
+        if (!warm) k_fill<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, 0.0);
         k_dot2<double><<<W.nb, TPB, 0, s>>>(W, c.b.p, c.b.p, c.part.p, PSTRIDE);
         k_fin<<<1, 1024, 0, s>>>(c.part.p, PSTRIDE, W.nb, FIN_SUM, S_TMP2, 0.0, c.sc.p);
         IBM_LAUNCH_CHECK();
@@ -964,7 +961,12 @@ int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s)
         double prev = HUGE_VAL;
         bool inner_failed = false;
         for (outer = 0; outer <= o.max_outer; ++outer) {
-            if (bn2 == 0.0) { rc = IBM_OK; rel = 0.0; break; }
+            if (bn2 == 0.0) {
+                k_fill<double><<<W.nb, TPB, 0, s>>>(W, c.x.p, 0.0);
+                rc = IBM_OK;
+                rel = 0.0;
+                break;
+            }
             // r64 = b - A x (pinned) and its norm
             int np = launch_apply<double>(c, M_PINNED, true, 2, c.x.p, c.r.p, c.b.p, nullptr, c.b.p, nullptr, s);
             k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
@@ -1106,6 +1108,73 @@ extern "C" int32_t poisson_solve(poisson_ctx *c, const double *f_dev, const doub
     });
 }
 
+extern "C" int32_t poisson_solve_from(poisson_ctx *c, const double *f_dev, const double *g_dev, const double *x0_dev,
+                                      int64_t n_x0, double *x_dev, poisson_stats *stats, void *stream)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c && f_dev && x0_dev && x_dev, IBM_EINVAL, "null argument");
+        IBM_REQUIRE(n_x0 == c->N || n_x0 == c->N + c->nm, IBM_EINVAL, "initial guess must hold N or N + n_mghost values");
+        StreamJoin j(*c, (hipStream_t)stream);
+        hipStream_t s = c->cs;
+        IBM_HIP(hipEventRecord(c->e0, s));
+        assemble_rhs(*c, f_dev, g_dev, c->b.p, s);
+        // initial guess: the cells (and membrane ghost unknowns when given)
+        // from x0, inactive slots zero, shifted to a zero pin value
+        const bool ghosts = n_x0 > c->N;
+        k_to_split<double, double><<<c->W0.nb, TPB, 0, s>>>(c->L0(), c->W0, x0_dev, c->x.p, ghosts ? c->nm : 0);
+        if (c->nm && !ghosts)
+            k_warm_membrane<<<(int)std::min<long long>((c->nm + TPB - 1) / TPB, 4096), TPB, 0, s>>>(c->sp, c->x.p);
+        k_zero_inactive<<<c->Wc.nb, TPB, 0, s>>>(c->L0(), c->Wc, c->x.p);
+        k_shift<double><<<c->W0.nb, TPB, 0, s>>>(c->L0(), c->W0, c->pin, c->x.p);
+        k_shift_pin<<<1, 1, 0, s>>>(c->pin, c->x.p);
+        IBM_LAUNCH_CHECK();
+        int rc = solve_core(*c, stats, s, true);
+        k_pinres<<<1, 64, 0, s>>>(c->L0(), c->pin, c->x.p, c->sc.p);
+        k_vsum<double, false><<<c->Wc.nb, TPB, 0, s>>>(c->L0(), c->Wc, c->x.p, c->part.p);
+        fin(*c, c->Wc.nb, FIN_MEAN, S_TMP2, c->vol_fluid, s);
+        k_gauge<<<c->W0.nb, TPB, 0, s>>>(c->L0(), c->W0, c->x.p, c->sc.p, S_TMP2, c->t.p);
+        from_split(*c, c->t.p, x_dev, c->nm, s);
+        IBM_HIP(hipEventRecord(c->e1, s));
+        read_scalars(*c, s);
+        if (stats) {
+            float ms = 0.f;
+            IBM_HIP(hipEventElapsedTime(&ms, c->e0, c->e1));
+            stats->solve_ms = ms;
+            stats->pin_residual = c->hsc[S_TMP];
+        }
+        if (rc == IBM_ENOCONV) throw Error(IBM_ENOCONV, "iteration limit reached");
+        if (rc == IBM_EBREAKDOWN) throw Error(IBM_EBREAKDOWN, "BiCGSTAB breakdown or non-finite values");
+    });
+}
+
+extern "C" int32_t poisson_update(poisson_ctx *c, const uint8_t *flags_dev, const ibm_stencils *st)
+{
+    return guarded([&] {
+        IBM_REQUIRE(c && flags_dev && st, IBM_EINVAL, "null argument");
+        setup_geometry(*c, flags_dev, st);
+    });
+}
+
+extern "C" int32_t ibm_fill_fresh(const ibm_grid *grid, const uint8_t *flags_old_dev, const uint8_t *flags_new_dev,
+                                  double *x_dev, int64_t *n_fresh, void *stream)
+{
+    return guarded([&] {
+        IBM_REQUIRE(grid && flags_old_dev && flags_new_dev && x_dev, IBM_EINVAL, "null argument");
+        const HostGrid g = read_grid(grid);
+        const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+        hipStream_t s = (hipStream_t)stream;
+        DBuf<int> cnt(1);
+        IBM_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
+        const int nb = (int)std::min<long long>(std::max<long long>((N + TPB - 1) / TPB, 1), 8192);
+        k_fill_fresh<<<nb, TPB, 0, s>>>(g.n[0], g.n[1], g.n[2], flags_old_dev, flags_new_dev, x_dev, cnt.p);
+        IBM_LAUNCH_CHECK();
+        int h = 0;
+        IBM_HIP(hipMemcpyAsync(&h, cnt.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        if (n_fresh) *n_fresh = h;
+    });
+}
+
 extern "C" int32_t poisson_solve_assembled(poisson_ctx *c, const double *b_dev, double *x_dev, poisson_stats *stats,
                                            void *stream)
 {
@@ -1242,6 +1311,7 @@ extern "C" int32_t poisson_bind_workspace(poisson_ctx *c, void *ws_dev, size_t b
         // captured iterations hold the old addresses
         if (c->g64) { (void)hipGraphExecDestroy(c->g64); c->g64 = nullptr; }
         if (c->g32) { (void)hipGraphExecDestroy(c->g32); c->g32 = nullptr; }
+        if (c->g64w) { (void)hipGraphExecDestroy(c->g64w); c->g64w = nullptr; }
         char *base = (char *)ws_dev;
         size_t off = 0;
         for_scratch(*c, [&](auto &b) {

@@ -356,6 +356,33 @@ def spheres_case(n: int = 1024, seed: int = 4, count: int = 20, rhs: bool = True
     return p
 
 
+def flapping_case(n: int = 512, step: int = 0, period: int = 1600, seed: int = 5, rhs: bool = True,
+                  nc: int = 60, ns: int = 120) -> Problem:
+    """One time step of a moving-body sequence on the tanh-stretched grid: a
+    zero-thickness plate (chord 0.2 along x, span 0.4 along y from its root
+    at y = 0.3, mild camber) flapping about the x-parallel line through its
+    root with amplitude 0.5 rad, and a sphere (r 0.08, centre x = 0.3)
+    heaving in z with amplitude 0.1; both follow sin(2 pi step / period).
+    At 512^3 and period 1600 the plate tip moves at most 0.7 of the finest
+    cell per step and the sphere 0.4.  Noise RHS seeded by ``seed`` only, so
+    consecutive steps share f."""
+    f, beta = stretched_faces(n)
+    ph = 2 * math.pi * step / period
+    th = 0.5 * math.sin(ph)
+    root_y, cz = 0.3, 0.5
+    body = plate((0.6, root_y + 0.2, cz), 0.2, 0.4, nc, ns, 0.02, 0.0)
+    v = body.verts.copy()
+    dy, dz = v[:, 1] - root_y, v[:, 2] - cz
+    v[:, 1] = root_y + dy * math.cos(th) - dz * math.sin(th)
+    v[:, 2] = cz + dy * math.sin(th) + dz * math.cos(th)
+    bodies = [sphere((0.3, 0.5, 0.5 + 0.1 * math.sin(ph)), 0.08), Body(v, body.tris, KIND_MEMBRANE)]
+    p = Problem("flapping%d_step%d" % (n, step), f, f.copy(), f.copy(), bodies, tol=1e-8, mixed=True,
+                meta={"beta": beta, "theta": th, "step": step, "period": period})
+    if rhs:
+        p.f = noise_rhs(p.npts, seed + 2000)
+    return p
+
+
 def serving_request(rng: np.random.Generator, emin: int = 64, emax: int = 384) -> Problem:
     """One request of the serving stream: edge log-uniform in [emin, emax]
     rounded to a multiple of 32, cube or 2:1:1 box, 1-4 bodies."""

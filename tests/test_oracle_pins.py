@@ -458,3 +458,63 @@ def test_p11_srj_bicgstab_matches_direct(case):
     assert info.rc == 0
     xd = refpy.solve_direct(A, b, S.flags, S.st.nm)
     assert rel(x, xd) < 1e-10
+
+
+# ---------------------------------------------------------------- P12 fresh cells (moving bodies)
+def test_fill_fresh_hand_case():
+    """Hand-worked 4x3x3 grid: the fresh cell's mean uses only neighbours
+    that are fluid at both steps; a fresh cell with none keeps its value;
+    other cells are untouched."""
+    nx, ny, nz = 4, 3, 3
+    N = nx * ny * nz
+    idx = lambda i, j, k: i + nx * (j + ny * k)
+    fo = np.zeros(N, np.uint8)
+    fn = np.zeros(N, np.uint8)
+    x = np.arange(N, dtype=np.float64) * 0.5 + 1.0
+    p = idx(1, 1, 1)
+    fo[p] = oracle.F_SOLID                       # fresh
+    fo[idx(0, 1, 1)] = oracle.F_SOLID            # -x: solid before -> excluded
+    fn[idx(0, 1, 1)] = 0
+    fn[idx(2, 1, 1)] = oracle.F_SOLID            # +x: solid now -> excluded
+    fo[idx(1, 0, 1)] = oracle.F_SOLID | oracle.F_GHOST
+    fn[idx(1, 0, 1)] = oracle.F_SOLID | oracle.F_GHOST   # -y: solid at both -> excluded
+    # +y, -z, +z remain: values x[idx(1,2,1)], x[idx(1,1,0)], x[idx(1,1,2)]
+    q = idx(3, 2, 2)                             # corner fresh cell, all neighbours solid now
+    fo[q] = oracle.F_SOLID
+    for nb in (idx(2, 2, 2), idx(3, 1, 2), idx(3, 2, 1)):
+        fn[nb] = oracle.F_SOLID
+    out, n = oracle.fill_fresh(nx, ny, nz, fo, fn, x)
+    want = (x[idx(1, 2, 1)] + x[idx(1, 1, 0)] + x[idx(1, 1, 2)]) / 3
+    # idx(0,1,1) is fluid now and was solid: fresh too, with neighbours
+    # +x (fresh p: solid before, excluded), -y, +y, -z, +z
+    w2 = (x[idx(0, 0, 1)] + x[idx(0, 2, 1)] + x[idx(0, 1, 0)] + x[idx(0, 1, 2)]) / 4
+    assert n == 3
+    assert out[p] == want and out[idx(0, 1, 1)] == w2 and out[q] == x[q]
+    others = np.ones(N, bool)
+    others[[p, q, idx(0, 1, 1)]] = False
+    assert np.array_equal(out[others], x[others])
+
+
+def test_fill_fresh_reproduces_constant_and_linear_fields():
+    """A constant field is reproduced exactly; a field linear in x is
+    reproduced at fresh cells whose +-x neighbours are the only valid ones."""
+    rng = np.random.default_rng(7)
+    nx, ny, nz = 12, 10, 9
+    N = nx * ny * nz
+    fo = np.where(rng.uniform(size=N) < 0.2, oracle.F_SOLID, 0).astype(np.uint8)
+    fn = np.where(rng.uniform(size=N) < 0.2, oracle.F_SOLID, 0).astype(np.uint8)
+    out, n = oracle.fill_fresh(nx, ny, nz, fo, fn, np.full(N, 3.25))
+    assert n == int(np.sum(((fn & 1) == 0) & ((fo & 1) != 0))) and n > 0
+    assert np.all(out == 3.25)
+    # linear in i: a fresh cell whose y/z neighbours are solid now
+    idx = lambda i, j, k: i + nx * (j + ny * k)
+    fo = np.zeros(N, np.uint8)
+    fn = np.zeros(N, np.uint8)
+    p = idx(5, 4, 4)
+    fo[p] = oracle.F_SOLID
+    for nb in (idx(5, 3, 4), idx(5, 5, 4), idx(5, 4, 3), idx(5, 4, 5)):
+        fn[nb] = oracle.F_SOLID
+    x = np.tile(np.arange(nx, dtype=np.float64) * 0.125, ny * nz)
+    x[p] = 99.0
+    out, n = oracle.fill_fresh(nx, ny, nz, fo, fn, x)
+    assert n == 1 and out[p] == 5 * 0.125
