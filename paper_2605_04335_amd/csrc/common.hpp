@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
+#include <shared_mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -56,6 +58,16 @@ int32_t guarded(F &&f)
 }
 
 // ---------------------------------------------------------------- memory
+// A graph capture in one thread excludes the library's device allocations
+// and frees in every other thread (the runtime treats them as synchronising
+// calls, which a capture in flight does not allow): captures hold this
+// exclusively, allocations and frees share it.
+inline std::shared_mutex &capture_mutex()
+{
+    static std::shared_mutex m;
+    return m;
+}
+
 // Owning device buffer (hipMalloc / hipFree).
 template <class T>
 struct DBuf {
@@ -86,7 +98,11 @@ struct DBuf {
         own = true;
         n = count;
         if (count) {
-            hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+            hipError_t e;
+            {
+                std::shared_lock<std::shared_mutex> lk(capture_mutex());
+                e = hipMalloc((void **)&p, count * sizeof(T));
+            }
             if (e != hipSuccess) {
                 p = nullptr;
                 n = 0;
@@ -98,7 +114,10 @@ struct DBuf {
     }
     void release()
     {
-        if (p && own) (void)hipFree(p);
+        if (p && own) {
+            std::shared_lock<std::shared_mutex> lk(capture_mutex());
+            (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
         own = true;

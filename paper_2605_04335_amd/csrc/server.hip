@@ -10,6 +10,8 @@
 
 #include "common.hpp"
 
+#include <cstdio>
+#include <cstdlib>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -171,6 +173,7 @@ void poisson_server::run_request(Request *r)
         err = e.what();
     }
     if (s) (void)hipStreamDestroy(s);
+    if (rc != IBM_OK && getenv("IBM_LOG")) fprintf(stderr, "[ibm] request failed (%d): %s\n", rc, err.c_str());
     std::lock_guard<std::mutex> lk(mu);
     r->rc = rc;
     r->err = err;

@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 
 namespace ibm {
@@ -103,6 +104,35 @@ inline long long host_slot(int H, int ny, long long Nh, int i, int j, int k)
 
 using namespace ibm;
 
+namespace ibm {
+namespace {
+// Pinned host slots for the per-context scalar read-back, cut from chunks
+// that live until the process ends: freeing pinned memory synchronises the
+// device, which a graph capture running in another thread does not allow.
+std::mutex g_pin_mu;
+std::vector<double *> g_pin_free;
+double *pinned_slot()
+{
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (g_pin_free.empty()) {
+        constexpr int per = 64;
+        double *chunk = nullptr;
+        std::shared_lock<std::shared_mutex> cl(capture_mutex());
+        IBM_HIP(hipHostMalloc((void **)&chunk, per * S_COUNT * sizeof(double), hipHostMallocDefault));
+        for (int q = per - 1; q >= 0; --q) g_pin_free.push_back(chunk + q * S_COUNT);
+    }
+    double *p = g_pin_free.back();
+    g_pin_free.pop_back();
+    return p;
+}
+void pinned_release(double *p)
+{
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_free.push_back(p);
+}
+}  // namespace
+}  // namespace ibm
+
 struct poisson_ctx {
     poisson_opts opts;
     HostGrid g;
@@ -152,7 +182,7 @@ struct poisson_ctx {
         if (g64) (void)hipGraphExecDestroy(g64);
         if (g32) (void)hipGraphExecDestroy(g32);
         if (g64w) (void)hipGraphExecDestroy(g64w);
-        if (hsc) (void)hipHostFree(hsc);
+        if (hsc) pinned_release(hsc);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         if (ej) (void)hipEventDestroy(ej);
@@ -492,14 +522,34 @@ int bicgstab(poisson_ctx &c, const T *rhs, TX *y, T *r, T *rh, T *p, T *v, T *ph
     }
     const bool use_graph = c.opts.use_graph && c.prof_kernel < 0;
     if (use_graph && !*graph) {
-        hipGraph_t gr;
-        c.capturing = true;
-        IBM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        bicg_iteration<T, TX>(c, y, r, rh, p, v, ph, sh, t, s);
-        IBM_HIP(hipStreamEndCapture(s, &gr));
-        c.capturing = false;
-        IBM_HIP(hipGraphInstantiate(graph, gr, nullptr, nullptr, 0));
-        IBM_HIP(hipGraphDestroy(gr));
+        // a failure inside the capture still ends it, so the stream never
+        // stays in capture mode (the user's stream joins it afterwards)
+        struct Capture {
+            poisson_ctx &c;
+            hipStream_t s;
+            hipGraph_t gr = nullptr;
+            bool open = false;
+            ~Capture()
+            {
+                if (open) {
+                    hipGraph_t g2 = nullptr;
+                    if (hipStreamEndCapture(s, &g2) == hipSuccess && g2) (void)hipGraphDestroy(g2);
+                    (void)hipGetLastError();
+                }
+                if (gr) (void)hipGraphDestroy(gr);
+                c.capturing = false;
+            }
+        } cap{c, s};
+        {
+            std::unique_lock<std::shared_mutex> lk(capture_mutex());
+            c.capturing = true;
+            IBM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            cap.open = true;
+            bicg_iteration<T, TX>(c, y, r, rh, p, v, ph, sh, t, s);
+            cap.open = false;
+            IBM_HIP(hipStreamEndCapture(s, &cap.gr));
+        }
+        IBM_HIP(hipGraphInstantiate(graph, cap.gr, nullptr, nullptr, 0));
     }
     int it = 0;
     double rel = 1.0;
@@ -752,7 +802,7 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
     IBM_HIP(hipEventCreate(&c->e0));
     IBM_HIP(hipEventCreate(&c->e1));
     IBM_HIP(hipEventCreateWithFlags(&c->ej, hipEventDisableTiming));
-    IBM_HIP(hipHostMalloc((void **)&c->hsc, S_COUNT * sizeof(double), hipHostMallocDefault));
+    c->hsc = pinned_slot();
     hipStream_t s = c->cs;
     const HostGrid &g = c->g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];

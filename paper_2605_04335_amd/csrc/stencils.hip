@@ -420,7 +420,8 @@ void build_stencils(const ibm_grid *grid, const ibm_body *bodies, int n_body, co
             int64_t np = compact_cells(flags, N, F_PIN, pl, s);
             IBM_REQUIRE(np == 1, IBM_EGEOM, "flags must hold exactly one pin cell");
             int32_t pin;
-            IBM_HIP(hipMemcpy(&pin, pl.p, 4, hipMemcpyDeviceToHost));
+            IBM_HIP(hipMemcpyAsync(&pin, pl.p, 4, hipMemcpyDeviceToHost, s));
+            IBM_HIP(hipStreamSynchronize(s));
             S->pin = pin;
         }
         if (rows > 0) {
@@ -526,13 +527,22 @@ extern "C" int32_t ibm_stencils_export(const ibm_stencils *s, int32_t *cell, int
         IBM_REQUIRE(s, IBM_EINVAL, "null stencils");
         size_t rows = (size_t)(s->ng + s->nm);
         if (!rows) return;
-        if (cell) IBM_HIP(hipMemcpy(cell, s->cell.p, rows * 4, hipMemcpyDeviceToHost));
-        if (col) IBM_HIP(hipMemcpy(col, s->col.p, rows * 32, hipMemcpyDeviceToHost));
-        if (w) IBM_HIP(hipMemcpy(w, s->w.p, rows * 64, hipMemcpyDeviceToHost));
-        if (sG) IBM_HIP(hipMemcpy(sG, s->sG.p, rows * 8, hipMemcpyDeviceToHost));
-        if (dlb) IBM_HIP(hipMemcpy(dlb, s->dlb.p, rows * 8, hipMemcpyDeviceToHost));
-        if (rflags) IBM_HIP(hipMemcpy(rflags, s->rfl.p, rows, hipMemcpyDeviceToHost));
-        if (geo) IBM_HIP(hipMemcpy(geo, s->geo.p, rows * 96, hipMemcpyDeviceToHost));
+        // copies on a private non-blocking stream: nothing here touches the
+        // legacy stream, which may not depend on another thread's capture
+        hipStream_t st = nullptr;
+        IBM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        struct Del {
+            hipStream_t q;
+            ~Del() { (void)hipStreamDestroy(q); }
+        } del{st};
+        if (cell) IBM_HIP(hipMemcpyAsync(cell, s->cell.p, rows * 4, hipMemcpyDeviceToHost, st));
+        if (col) IBM_HIP(hipMemcpyAsync(col, s->col.p, rows * 32, hipMemcpyDeviceToHost, st));
+        if (w) IBM_HIP(hipMemcpyAsync(w, s->w.p, rows * 64, hipMemcpyDeviceToHost, st));
+        if (sG) IBM_HIP(hipMemcpyAsync(sG, s->sG.p, rows * 8, hipMemcpyDeviceToHost, st));
+        if (dlb) IBM_HIP(hipMemcpyAsync(dlb, s->dlb.p, rows * 8, hipMemcpyDeviceToHost, st));
+        if (rflags) IBM_HIP(hipMemcpyAsync(rflags, s->rfl.p, rows, hipMemcpyDeviceToHost, st));
+        if (geo) IBM_HIP(hipMemcpyAsync(geo, s->geo.p, rows * 96, hipMemcpyDeviceToHost, st));
+        IBM_HIP(hipStreamSynchronize(st));
     });
 }
 

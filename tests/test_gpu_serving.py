@@ -184,3 +184,22 @@ def test_setup_cache(P):
         assert hits == [0, 0, 0]
     finally:
         srv.close()
+
+
+def test_burst_with_cache_all_succeed(P):
+    """Requests arriving together, with new set-ups (and their first graph
+    captures) overlapping cached ones and evictions: every one succeeds.
+    Guards against runtime calls that a graph capture in another worker
+    thread does not allow (synchronous legacy-stream copies, frees)."""
+    reqs = requests(12, 15, 32, 96)
+    srv = P.Server(hbm_budget=16 << 30, max_slots=4, cache_entries=3)
+    try:
+        for rnd in range(2):
+            tickets = [srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, precision="mixed", tol=1e-8) for p in reqs]
+            res = wait_all(P, srv, tickets)
+            bad = [(q, r[0], r[3].rel_residual) for q, r in enumerate(res[t] for t in tickets)
+                   if r[0] != P.IBM_OK or r[3].rel_residual > 1e-8]
+            say("round", rnd, "failures", bad)
+            assert not bad
+    finally:
+        srv.close()
