@@ -136,6 +136,61 @@ def serving_bench(P, rates, nreq, seed=5, slots=4, budget=64 << 30):
             "max_slots": slots, "hbm_budget_GB": budget >> 30, "sweep": out}
 
 
+def moving_bench(P, n=512, steps=3):
+    """Moving-body time steps (flapping plate + heaving sphere, stretched
+    grid, mixed MG-BiCGSTAB to 1e-8): per step re-classification, ghost
+    rows, context update, fresh-cell fill, the solve from the previous
+    pressure and the nodal pressure forces, each timed with a device
+    synchronisation around it."""
+    import torch
+    from paper_2605_04335_amd import workloads as W
+
+    def now():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
+    p = W.flapping_case(n, 0)
+    fl, st, sol, _ = P.setup(p.xf, p.yf, p.zf, p.bodies, precision="mixed", tol=1e-8, max_iter=100)
+    f = torch.from_numpy(p.f).cuda()
+    x, s = sol.solve(f)
+    rows = []
+    for k in range(1, steps + 1):
+        q = W.flapping_case(n, k)
+        t0 = now()
+        fq, cq = P.classify(q.xf, q.yf, q.zf, q.bodies)
+        t1 = now()
+        sq = P.build_ghost_stencils(q.xf, q.yf, q.zf, q.bodies, fq)
+        t2 = now()
+        sol.update(fq, sq)
+        t3 = now()
+        x0 = x[: q.npts].clone()
+        nf = P.fill_fresh(q.xf, q.yf, q.zf, fl, fq, x0)
+        t4 = now()
+        x, s = sol.solve_from(f, x0)
+        t5 = now()
+        F, dp, lost = P.surface_forces(q.xf, q.yf, q.zf, q.bodies, fq, x)
+        t6 = now()
+        rows.append({"classify_ms": (t1 - t0) * 1e3, "stencils_ms": (t2 - t1) * 1e3, "update_ms": (t3 - t2) * 1e3,
+                     "fresh_ms": (t4 - t3) * 1e3, "solve_ms": (t5 - t4) * 1e3, "forces_ms": (t6 - t5) * 1e3,
+                     "iterations": s.iterations,
+                     "fresh_cells": nf, "ghosts": cq["n_ghost"], "membrane_ghosts": cq["n_mghost"],
+                     "ok": int(s.status == 0 and s.rel_residual <= 1e-8)})
+        fl = fq
+        log("moving step %d: classify %.1f stencils %.1f update %.1f fresh %.1f solve %.1f forces %.1f ms (%d its)" %
+            (k, *(rows[-1][c] for c in ("classify_ms", "stencils_ms", "update_ms", "fresh_ms", "solve_ms",
+                                        "forces_ms")), s.iterations))
+    del sol
+    torch.cuda.empty_cache()
+    mean = {c: round(float(np.mean([r[c] for r in rows])), 2)
+            for c in ("classify_ms", "stencils_ms", "update_ms", "fresh_ms", "solve_ms", "forces_ms", "iterations")}
+    resetup = mean["classify_ms"] + mean["stencils_ms"] + mean["update_ms"] + mean["fresh_ms"]
+    return {"workload": "flapping plate (14.4k triangles) + heaving sphere, %d^3 tanh-stretched, noise RHS, "
+                        "mixed MG-BiCGSTAB to 1e-8 from the previous step's pressure" % n,
+            "steps": steps, "mean": mean, "resetup_ms": round(resetup, 2),
+            "ms_per_step": round(resetup + mean["solve_ms"] + mean["forces_ms"], 2),
+            "ok": sum(r["ok"] for r in rows)}
+
+
 def cpu_baseline(cfg, budget_s):
     """The FP64 oracle on a bounded sample of the same workload recipe."""
     import oracle
@@ -171,6 +226,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-moving", action="store_true", help="skip the moving-body time-step measurement")
     ap.add_argument("--serve-rates", default="5,20,80", help="request arrival rates (req/s) of the serving sweep")
     ap.add_argument("--serve-requests", type=int, default=24, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -275,6 +331,8 @@ def main():
                                                                                    ms64 / ms_per_step, err))
     if not args.no_serve:
         out["serving"] = serving_bench(P, [float(r) for r in args.serve_rates.split(",")], args.serve_requests)
+    if not args.no_moving:
+        out["moving"] = moving_bench(P)
     if args.copy_calibration:
         import torch as _t
         nbytes = 1 << 30

@@ -217,6 +217,28 @@ int32_t poisson_solve(poisson_ctx *ctx, const double *f_dev, const double *g_dev
                       poisson_stats *stats, void *stream);
 
 /*
+ * ibm_surface_forces -- pressure loads on the bodies (Sec. 2.3.1, Eq. fext
+ * without the shear term; the surface pressure handed to the structural
+ * solver each step, Sec. 2.4).  Per triangle: centroid c, area A, unit
+ * normal n = (v1-v0) x (v2-v0) / |.| (vertex order; outward for closed
+ * bodies), probe distance d = 2 max(w_x, w_y, w_z) of the cell holding c.
+ * p+ is the trilinear interpolation of the cell pressures at c + d n (box
+ * clamped to the outermost centres; nodes in solid non-ghost cells dropped,
+ * remaining weights renormalised); membranes also take p- at c - d n.
+ * dp = p+ - p- (membrane) or p+ (closed body, fluid outside).  Each node of
+ * the triangle receives -(1/3) dp n A, summed per node in a fixed order.
+ *   flags_dev: device uint8[N] (ibm_classify); p_dev: device double[>= N],
+ *   cell pressures in natural order (a poisson_solve output);
+ *   force_dev: device double[3 * total vertices], body by body (output);
+ *   dp_dev: device double[total triangles] or NULL (output);
+ *   n_lost (may be NULL): probes with no usable node (their p is 0).
+ * Synchronous with stream.  IBM_EINVAL for null pointers or empty bodies,
+ * IBM_EGEOM for triangle indices out of range.
+ */
+int32_t ibm_surface_forces(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body, const uint8_t *flags_dev,
+                           const double *p_dev, double *force_dev, double *dp_dev, int64_t *n_lost, void *stream);
+
+/*
  * Moving bodies (the paper's time loop, Sec. 2.4 and 2.5: every step
  * re-classifies the grid and rebuilds the ghost rows before the PPE).
  *

@@ -333,3 +333,85 @@ def fill_fresh(nx, ny, nz, flags_old, flags_new, x) -> Tuple[np.ndarray, int]:
         if cnt:
             out[p] = acc / cnt
     return out, len(fresh)
+
+
+# --------------------------------------------------------------------------
+# Surface loads (Sec. 2.3.1, Eq. fext, pressure part)
+def _trilinear(centres, field3, flags3, pts):
+    """Trilinear interpolation of a cell-centred field at points: the box of
+    the eight centres around each point (clamped to the outermost centres),
+    nodes in solid non-ghost cells dropped and the remaining weights
+    renormalised; (values, number of points with no valid node)."""
+    n = [len(c) for c in centres]
+    idx, frac = [], []
+    for d in range(3):
+        c = centres[d]
+        i0 = np.clip(np.searchsorted(c, pts[:, d], side="right") - 1, 0, n[d] - 2)
+        t = (pts[:, d] - c[i0]) / (c[i0 + 1] - c[i0])
+        idx.append(i0)
+        frac.append(np.clip(t, 0.0, 1.0))
+    num = np.zeros(len(pts))
+    den = np.zeros(len(pts))
+    for q in range(8):
+        o = [(q >> d) & 1 for d in range(3)]
+        w = np.ones(len(pts))
+        for d in range(3):
+            w = w * (frac[d] if o[d] else 1.0 - frac[d])
+        ii, jj, kk = idx[0] + o[0], idx[1] + o[1], idx[2] + o[2]
+        f = flags3[kk, jj, ii]
+        ok = ((f & F_SOLID) == 0) | ((f & F_GHOST) != 0)
+        w = np.where(ok, w, 0.0)
+        num = num + w * field3[kk, jj, ii]
+        den = den + w
+    val = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+    return val, int(np.sum(den == 0))
+
+
+def surface_forces(xf, yf, zf, bodies, flags, p):
+    """Nodal pressure forces on every body (plain definition, not tuned).
+
+    Per triangle j (vertices in the body's order): centroid c, area A, unit
+    normal n = (v1 - v0) x (v2 - v0) / |.|, and probe distance d = 2 max of
+    the widths of the cell that contains c.  p+ is the pressure interpolated
+    at c + d n; for a membrane p- at c - d n and dp = p+ - p-, for a closed
+    body (outward normals, fluid outside) dp = p+.  Each of the triangle's
+    three nodes receives -(1/3) dp n A (the area rule of Eq. fext without
+    the shear term).  Returns (list of (n_vert, 3) forces per body, per-body
+    dp arrays, number of probes with no valid interpolation node)."""
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    faces = [xf, yf, zf]
+    centres = [0.5 * (f[1:] + f[:-1]) for f in faces]
+    widths = [np.diff(f) for f in faces]
+    n = [len(c) for c in centres]
+    f3 = np.asarray(flags, dtype=np.uint8).reshape(n[2], n[1], n[0])
+    p3 = np.asarray(p, dtype=np.float64)[: n[0] * n[1] * n[2]].reshape(n[2], n[1], n[0])
+    forces, dps, lost = [], [], 0
+    for b in bodies:
+        v = np.asarray(b.verts, dtype=np.float64)
+        t = np.asarray(b.tris, dtype=np.int64)
+        a, bb, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+        cen = (a + bb + c) / 3.0
+        cr = np.cross(bb - a, c - a)
+        nrm = np.linalg.norm(cr, axis=1)
+        un = cr / nrm[:, None]
+        area = 0.5 * nrm
+        h = np.zeros(len(t))
+        for d in range(3):
+            k = np.clip(np.searchsorted(faces[d], cen[:, d], side="right") - 1, 0, n[d] - 1)
+            h = np.maximum(h, widths[d][k])
+        dist = 2.0 * h
+        pp, l1 = _trilinear(centres, p3, f3, cen + dist[:, None] * un)
+        lost += l1
+        if b.kind == 1:
+            pm, l2 = _trilinear(centres, p3, f3, cen - dist[:, None] * un)
+            lost += l2
+            dp = pp - pm
+        else:
+            dp = pp
+        contrib = -(dp * area)[:, None] * un / 3.0
+        F = np.zeros((len(v), 3))
+        for m in range(3):
+            np.add.at(F, t[:, m], contrib)
+        forces.append(F)
+        dps.append(dp)
+    return forces, dps, lost

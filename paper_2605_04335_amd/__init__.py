@@ -86,7 +86,7 @@ EXPORTS = ["ibm_classify", "ibm_build_ghost_stencils", "ibm_stencils_info", "ibm
            "poisson_solve", "poisson_apply", "poisson_assemble_rhs", "poisson_precond", "poisson_solve_assembled",
            "poisson_destroy", "poisson_workspace_size", "poisson_bind_workspace", "poisson_server_create",
            "poisson_submit", "poisson_poll", "poisson_server_drain", "poisson_server_destroy", "ibm_last_error",
-           "poisson_update", "poisson_solve_from", "ibm_fill_fresh"]
+           "poisson_update", "poisson_solve_from", "ibm_fill_fresh", "ibm_surface_forces"]
 
 _lib = None
 
@@ -187,6 +187,23 @@ def fill_fresh(xf, yf, zf, flags_old, flags_new, x) -> int:
     _check(lib().ibm_fill_fresh(ctypes.byref(G.g), _tptr(flags_old), _tptr(flags_new), _tptr(x), ctypes.byref(n),
                                 _stream()), "ibm_fill_fresh")
     return n.value
+
+
+def surface_forces(xf, yf, zf, bodies, flags, p):
+    """Nodal pressure forces (device double[total vertices, 3], body by
+    body), per-triangle pressure jumps (device double[total triangles]) and
+    the count of probes with no usable interpolation node."""
+    import torch
+    G = _GridArgs(xf, yf, zf)
+    B = _BodyArgs(bodies)
+    nv = sum(len(b.verts) for b in bodies)
+    nt = sum(len(b.tris) for b in bodies)
+    F = torch.zeros((max(nv, 1), 3), dtype=torch.float64, device=p.device)
+    dp = torch.zeros(max(nt, 1), dtype=torch.float64, device=p.device)
+    lost = ctypes.c_int64()
+    _check(lib().ibm_surface_forces(ctypes.byref(G.g), B.arr, ctypes.c_int32(B.n), _tptr(flags), _tptr(p), _tptr(F),
+                                    _tptr(dp), ctypes.byref(lost), _stream()), "ibm_surface_forces")
+    return F[:nv], dp[:nt], lost.value
 
 
 class Stencils:

@@ -1,9 +1,10 @@
 """Builds libibmpoisson.so (hipcc, gfx950) in-tree.
 
 Every translation unit is compiled for gfx950 only with packed-FP32
-instructions disabled; the classification and ghost-stencil units are
-compiled without FMA contraction so their quantisation, predicates and
-distance comparisons round exactly as written.
+instructions disabled; the classification, ghost-stencil and surface-load
+units are compiled without FMA contraction so their quantisation,
+predicates, distance comparisons and interpolations round exactly as
+written.
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ UNITS = {
     "stencils.hip": ["-ffp-contract=off"],
     "solver.hip": [],
     "server.hip": [],
+    "forces.hip": ["-ffp-contract=off"],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

@@ -518,3 +518,61 @@ def test_fill_fresh_reproduces_constant_and_linear_fields():
     x[p] = 99.0
     out, n = oracle.fill_fresh(nx, ny, nz, fo, fn, x)
     assert n == 1 and out[p] == 5 * 0.125
+
+
+# ---------------------------------------------------------------- P13 surface loads
+def _uniform(n):
+    return W.uniform_faces(n)
+
+
+def test_surface_forces_box_in_linear_field():
+    """Closed cube of side L on a uniform grid (probe distance d = 2h) in
+    p = a.x: trilinear interpolation of a linear field is exact, the centroid
+    rule integrates it exactly, so the total force is
+    -(a L^3 + 2 d L^2 a) (divergence theorem plus the probe offset)."""
+    n = 40
+    f = _uniform(n)
+    h = 1.0 / n
+    lo, hi = np.array([0.3137, 0.2911, 0.3323]), np.array([0.6589, 0.6402, 0.6871])
+    L = hi - lo
+    body = W.box(lo, hi)
+    flags = oracle.classify(f, f, f, [body])
+    c = W.centres(f)
+    a = np.array([0.7, -1.3, 2.1])
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    p = (a[0] * X + a[1] * Y + a[2] * Z).ravel()
+    F, dp, lost = oracle.surface_forces(f, f, f, [body], flags, p)
+    assert lost == 0
+    tot = F[0].sum(axis=0)
+    d = 2 * h
+    vol = np.prod(L)
+    side = np.array([L[1] * L[2], L[0] * L[2], L[0] * L[1]])
+    want = -(a * vol + 2 * d * a * side)
+    assert np.allclose(tot, want, rtol=1e-12, atol=1e-14)
+
+
+def test_surface_forces_plate_jump_and_constant_sphere():
+    """Flat membrane (normal +z) in p = a.x: dp = 2 d a_z on every triangle,
+    total force -2 d a_z A e_z; a constant field on a closed sphere gives
+    zero total force while every nodal force is non-zero."""
+    n = 48
+    f = _uniform(n)
+    h = 1.0 / n
+    plate = W.plate((0.5, 0.5, 0.5 + 0.25 * h), 0.3, 0.4, 12, 16)
+    flags = oracle.classify(f, f, f, [plate])
+    c = W.centres(f)
+    a = np.array([0.4, 0.9, -1.7])
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    p = (a[0] * X + a[1] * Y + a[2] * Z).ravel()
+    F, dp, lost = oracle.surface_forces(f, f, f, [plate], flags, p)
+    assert lost == 0
+    d = 2 * h
+    assert np.allclose(dp[0], 2 * d * a[2], rtol=1e-11, atol=0)
+    tot = F[0].sum(axis=0)
+    assert np.allclose(tot, [0, 0, -2 * d * a[2] * 0.3 * 0.4], rtol=1e-11, atol=1e-15)
+    sph = W.sphere((0.5, 0.5, 0.5), 0.2, freq=6)
+    flags = oracle.classify(f, f, f, [sph])
+    F, dp, lost = oracle.surface_forces(f, f, f, [sph], flags, np.full(n ** 3, 2.5))
+    assert lost == 0 and np.allclose(dp[0], 2.5)
+    assert np.abs(F[0].sum(axis=0)).max() < 1e-13
+    assert np.all(np.linalg.norm(F[0], axis=1) > 0)
