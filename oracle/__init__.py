@@ -123,7 +123,10 @@ def ghost_lists(flags: np.ndarray):
     return gcell, mcell, mg_of
 
 
-def stencils(xf, yf, zf, bodies, flags) -> Stencils:
+def stencils(xf, yf, zf, bodies, flags, bc: str = "neumann") -> Stencils:
+    """Ghost rows: Neumann rows of the pressure system (bc "neumann") or
+    Dirichlet rows of the advection-diffusion step (bc "dirichlet")."""
+    assert bc in ("neumann", "dirichlet")
     xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
     gcell, mcell, mg_of = ghost_lists(flags)
     rows = np.ascontiguousarray(np.concatenate([gcell, mcell]).astype(np.int32))
@@ -138,7 +141,8 @@ def stencils(xf, yf, zf, bodies, flags) -> Stencils:
     box = np.zeros((max(nr, 1), 3), dtype=np.int32)
     keep, bargs = _bodies_args(bodies)
     rc = lib().orc_ghost_stencils(*_grid_args(xf, yf, zf), *bargs, _p(flags), _p(mg_of), ctypes.c_int32(nr),
-                                  _p(rows), _p(mem), _p(col), _p(w), _p(sG), _p(dlb), _p(rfl), _p(geo), _p(box))
+                                  _p(rows), _p(mem), ctypes.c_int(1 if bc == "dirichlet" else 0), _p(col), _p(w),
+                                  _p(sG), _p(dlb), _p(rfl), _p(geo), _p(box))
     if rc != 0:
         raise ValueError("orc_ghost_stencils failed: %d" % rc)
     return Stencils(gcell, mcell, mg_of, col[:nr], w[:nr], sG[:nr], dlb[:nr], rfl[:nr], geo[:nr], box[:nr])
@@ -415,3 +419,77 @@ def surface_forces(xf, yf, zf, bodies, flags, p):
         forces.append(F)
         dps.append(dp)
     return forces, dps, lost
+
+
+# --------------------------------------------------------------------------
+# Advection-diffusion step (Sec. 2.1: SRJ for the momentum equations)
+def ad_schedule(m: int, beta: float, dg_max: float) -> np.ndarray:
+    """Relaxation factors of an m-sweep SRJ cycle for H = I - beta L: the
+    eigenvalues of D^-1 H lie in [a, 2 - a], a = 1 / (1 + beta dg_max), and
+    the factors are the reciprocals of the degree-m Chebyshev roots on that
+    interval, applied smallest, largest, second smallest, ..."""
+    a = 1.0 / (1.0 + beta * dg_max)
+    b = 2.0 - a
+    j = np.arange(1, m + 1)
+    kap = 0.5 * (a + b) - 0.5 * (b - a) * np.cos(np.pi * (2 * j - 1) / (2.0 * m))
+    w = np.sort(1.0 / kap)
+    order = []
+    lo, hi = 0, m - 1
+    while lo <= hi:
+        order.append(lo)
+        if hi != lo:
+            order.append(hi)
+        lo += 1
+        hi -= 1
+    return np.ascontiguousarray(w[order])
+
+
+def max_cell_scale(xf, yf, zf) -> float:
+    """Largest diagonal sum of the 7-point coefficients over the grid."""
+    parts = []
+    for f in (xf, yf, zf):
+        f = _f64(f)
+        c = 0.5 * (f[1:] + f[:-1])
+        w = np.diff(f)
+        n = len(w)
+        cp = np.zeros(n)
+        cm = np.zeros(n)
+        cp[:-1] = 1.0 / (w[:-1] * (c[1:] - c[:-1]))
+        cm[1:] = 1.0 / (w[1:] * (c[1:] - c[:-1]))
+        parts.append((cp + cm).max())
+    return float(sum(parts))
+
+
+def ad_apply(xf, yf, zf, flags, st: Stencils, beta, x) -> np.ndarray:
+    """y = H x for the advection-diffusion step (st: Dirichlet rows)."""
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    x = _f64(x)
+    y = np.zeros_like(x)
+    keep, a = _sys_args(xf, yf, zf, flags, st)
+    lib().orc_ad_apply(*a, ctypes.c_double(beta), _p(x), _p(y))
+    return y
+
+
+def ad_rhs(xf, yf, zf, flags, st: Stencils, f, g=None) -> np.ndarray:
+    """Right-hand side of the step: f on fluid cells, sG dlb g on ghost rows
+    (g: wall velocity at each row's BI; None for a wall at rest), 0 on solid cells."""
+    N = len(flags)
+    b = np.zeros(N + st.nm)
+    fl = np.asarray(flags)
+    b[:N] = np.where((fl & F_SOLID) == 0, _f64(f)[:N], 0.0)
+    rows = np.concatenate([st.gcell.astype(np.int64), N + np.arange(st.nm)])
+    b[rows] = 0.0 if g is None else st.sG * st.dlb * _f64(g)
+    return b
+
+
+def ad_solve(xf, yf, zf, flags, st: Stencils, beta, rhs, omega, tol=1e-10, maxcyc=1000, x0=None):
+    """SRJ cycles on H u = rhs; returns (u, cycles, relative residual, rc)."""
+    xf, yf, zf = _f64(xf), _f64(yf), _f64(zf)
+    rhs = _f64(rhs)
+    om = _f64(omega)
+    x = np.zeros_like(rhs) if x0 is None else _f64(x0).copy()
+    info = np.zeros(2)
+    keep, a = _sys_args(xf, yf, zf, flags, st)
+    rc = lib().orc_ad_solve(*a, ctypes.c_double(beta), _p(rhs), _p(x), ctypes.c_double(tol), ctypes.c_int(maxcyc),
+                            ctypes.c_int(len(om)), _p(om), _p(info))
+    return x, int(info[0]), float(info[1]), int(rc)

@@ -392,7 +392,12 @@ static double cell_scale(const Grid *g, int i, int j, int k)
 
 /*
  * Ghost-cell rows (Sec. 2.5 item 2; GCM of Mittal et al. 2008, read as the
- * standard image-point Neumann stencil).  Rows: closed ghosts and membrane
+ * standard image-point stencil).  bc 0: Neumann rows for the pressure,
+ * sG (sum w x - x_G) = sG (dl - beta_BI) g with a derivative row at BI when
+ * G is a node of the box.  bc 1: Dirichlet rows for the velocity of the
+ * advection-diffusion step (the value at BI is the mean of G and IP),
+ * sG (sum w x + x_G) = sG (2 - beta_BI) g with a value row at BI; a ghost on
+ * the surface (degenerate distance) gets x_G = g.  Rows: closed ghosts and membrane
  * ghost unknowns, given by row_cell[] and row_mem[] (1 for a membrane ghost
  * unknown).  mg_of[N] maps a cell to its membrane-ghost index or -1.
  * Outputs per row r:
@@ -407,7 +412,7 @@ static double cell_scale(const Grid *g, int i, int j, int k)
 int orc_ghost_stencils(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, int nbody,
                        const int32_t *kind, const int32_t *nvert, const int32_t *ntri, const double *verts,
                        const int32_t *tris, const uint8_t *flags, const int32_t *mg_of, int32_t nrows,
-                       const int32_t *row_cell, const int32_t *row_mem, int32_t *col, double *w, double *sG,
+                       const int32_t *row_cell, const int32_t *row_mem, int bc, int32_t *col, double *w, double *sG,
                        double *dlb, uint8_t *rfl, double *geo, int32_t *box)
 {
     Grid g;
@@ -502,6 +507,11 @@ int orc_ghost_stencils(int nx, int ny, int nz, const double *xf, const double *y
             int64_t id = IDX(g.n, ii, jj, kk);
             uint8_t f = flags[id];
             cl[m] = -1;
+            if (id == cell && bc == 1) {
+                basis(bil[0], bil[1], bil[2], V[m]);  /* value row at BI */
+                dnode = m;
+                continue;
+            }
             if (id == cell) {
                 double x = bil[0], y = bil[1], z = bil[2];
                 double gx[8] = {0, 1, 0, 0, y, 0, z, y * z};
@@ -543,7 +553,12 @@ int orc_ghost_stencils(int nx, int ny, int nz, const double *xf, const double *y
                 w[8 * r + m] = (cl[m] >= 0) ? beta[m] : 0.0;
             }
             if (dnode >= 0) { bbi = beta[dnode]; fl |= 2; }
-            dlb[r] = dl - bbi;
+            dlb[r] = bc == 1 ? 2.0 - bbi : dl - bbi;
+            if (bc == 1 && (fl & 4)) {
+                /* G on the surface: x_G = g */
+                for (int m = 0; m < 8; ++m) { col[8 * r + m] = -1; w[8 * r + m] = 0.0; }
+                dlb[r] = 1.0;
+            }
         } else {
             /* first-order fallback: mean of the face neighbours on the relevant side */
             fl |= 1;
@@ -566,7 +581,7 @@ int orc_ghost_stencils(int nx, int ny, int nz, const double *xf, const double *y
                 }
             for (int m = 0; m < 8; ++m) { col[8 * r + m] = -1; w[8 * r + m] = 0.0; }
             for (int m = 0; m < cnt; ++m) { col[8 * r + m] = nb[m]; w[8 * r + m] = 1.0 / cnt; }
-            dlb[r] = 0.0;
+            dlb[r] = bc == 1 ? 2.0 : 0.0;
             if (cnt == 0) rc = ORC_EGEOM;
         }
         sG[r] = s;
@@ -1378,3 +1393,109 @@ int orc_threads(void) { return omp_get_max_threads(); }
 #else
 int orc_threads(void) { return 1; }
 #endif
+
+/* ------------------------------------------------ advection-diffusion step */
+/*
+ * Implicit diffusion of one velocity component in the fractional step
+ * (Sec. 2.1: the advection-diffusion equations are solved with scheduled
+ * relaxed Jacobi).  H u = u - beta (L u) on fluid cells, L the 7-point
+ * operator of the pressure system (zero-flux walls, the neighbour across a
+ * cut membrane link is that neighbour's ghost unknown), beta = nu dt (times
+ * 1/2 for Crank-Nicolson); Dirichlet ghost rows sG (sum w u + u_G) from
+ * orc_ghost_stencils with bc 1; solid non-ghost rows 0.  No pin.
+ */
+static void ad_apply(const Sys *S, double beta, const double *x, double *y)
+{
+    const Grid *g = &S->g;
+    int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+#pragma omp parallel for
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int64_t p = IDX(g->n, i, j, k);
+                if (S->flags[p] & F_SOLID) y[p] = 0.0;
+                else y[p] = x[p] - beta * fluid_row(S, x, i, j, k, p);
+            }
+#pragma omp parallel for
+    for (int32_t r = 0; r < S->ng + S->nm; ++r) {
+        double acc = 0.0;
+        for (int m = 0; m < 8; ++m) {
+            int32_t c = S->col[8 * r + m];
+            if (c >= 0) acc += S->w[8 * r + m] * x[c];
+        }
+        int64_t u = row_unknown(S, r);
+        y[u] = S->sG[r] * (acc + x[u]);
+    }
+}
+
+void orc_ad_apply(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, const uint8_t *flags,
+                  const int32_t *mg_of, int32_t ng, int32_t nm, const int32_t *row_cell, const int32_t *col,
+                  const double *w, const double *sG, double beta, const double *x, double *y)
+{
+    Sys S;
+    if (sys_init(&S, nx, ny, nz, xf, yf, zf, flags, mg_of, ng, nm, row_cell, col, w, sG)) return;
+    ad_apply(&S, beta, x, y);
+    grid_free(&S.g);
+}
+
+/*
+ * SRJ solve of H u = rhs: cycles of m weighted Jacobi sweeps
+ * u <- u + omega_s D^-1 (rhs - H u), D the diagonal of H (1 + beta * sum c
+ * on fluid rows, sG on ghost rows), from the u given on entry, until the
+ * relative residual ||rhs - H u|| / ||rhs|| (checked after every cycle) is
+ * at most tol.  Solid non-ghost unknowns are left at 0.
+ * info[0] cycles, info[1] final relative residual.  Returns 0, or
+ * ORC_ENOCONV after maxcyc cycles.
+ */
+int orc_ad_solve(int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, const uint8_t *flags,
+                 const int32_t *mg_of, int32_t ng, int32_t nm, const int32_t *row_cell, const int32_t *col,
+                 const double *w, const double *sG, double beta, const double *rhs, double *x, double tol,
+                 int maxcyc, int m, const double *omega, double *info)
+{
+    Sys S;
+    if (sys_init(&S, nx, ny, nz, xf, yf, zf, flags, mg_of, ng, nm, row_cell, col, w, sG)) return ORC_EINVAL;
+    const Grid *g = &S.g;
+    int64_t n = S.N + nm;
+    double *dinv = calloc(n, 8), *y = malloc(8 * n);
+    for (int k = 0; k < g->n[2]; ++k)
+        for (int j = 0; j < g->n[1]; ++j)
+            for (int i = 0; i < g->n[0]; ++i) {
+                int64_t p = IDX(g->n, i, j, k);
+                if (!(flags[p] & F_SOLID)) dinv[p] = 1.0 / (1.0 + beta * cell_scale(g, i, j, k));
+            }
+    for (int32_t r = 0; r < ng + nm; ++r) dinv[row_unknown(&S, r)] = 1.0 / sG[r];
+    for (int64_t q = 0; q < n; ++q)
+        if (dinv[q] == 0.0) x[q] = 0.0;
+    double rn = 0.0;
+    for (int64_t q = 0; q < n; ++q) rn += rhs[q] * rhs[q];
+    rn = sqrt(rn);
+    int cyc = 0, rc = ORC_ENOCONV;
+    double rel = 0.0;
+    ad_apply(&S, beta, x, y);
+    {
+        double s2 = 0.0;
+        for (int64_t q = 0; q < n; ++q) s2 += (rhs[q] - y[q]) * (rhs[q] - y[q]);
+        rel = rn > 0.0 ? sqrt(s2) / rn : 0.0;
+    }
+    if (rel <= tol) rc = 0;
+    while (rc != 0 && cyc < maxcyc) {
+        for (int s = 0; s < m; ++s) {
+            if (s > 0) ad_apply(&S, beta, x, y);
+            const double om = omega[s];
+#pragma omp parallel for
+            for (int64_t q = 0; q < n; ++q) x[q] += om * dinv[q] * (rhs[q] - y[q]);
+        }
+        ++cyc;
+        ad_apply(&S, beta, x, y);
+        double s2 = 0.0;
+        for (int64_t q = 0; q < n; ++q) s2 += (rhs[q] - y[q]) * (rhs[q] - y[q]);
+        rel = rn > 0.0 ? sqrt(s2) / rn : 0.0;
+        if (rel <= tol) rc = 0;
+    }
+    info[0] = cyc;
+    info[1] = rel;
+    free(dinv);
+    free(y);
+    grid_free(&S.g);
+    return rc;
+}

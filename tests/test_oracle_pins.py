@@ -576,3 +576,102 @@ def test_surface_forces_plate_jump_and_constant_sphere():
     assert lost == 0 and np.allclose(dp[0], 2.5)
     assert np.abs(F[0].sum(axis=0)).max() < 1e-13
     assert np.all(np.linalg.norm(F[0], axis=1) > 0)
+
+
+# ---------------------------------------------------------------- P14 advection-diffusion step
+def _empty_case(nx, ny, nz):
+    xf, yf, zf = W.uniform_faces(nx), W.uniform_faces(ny, ny / nx), W.uniform_faces(nz, nz / nx)
+    flags = oracle.classify(xf, yf, zf, [])
+    st = oracle.stencils(xf, yf, zf, [], flags, bc="dirichlet")
+    return xf, yf, zf, flags, st
+
+
+def test_ad_operator_and_solve_on_neumann_eigenvectors():
+    """No bodies, zero-flux walls: products of cos(pi k (i+1/2)/n) are
+    eigenvectors of the discrete Laplacian with eigenvalue
+    -sum 4 sin^2(pi k_d / 2 n_d) / h^2, so H v = (1 + beta lam) v and the SRJ
+    solve of H u = v returns v / (1 + beta lam)."""
+    nx, ny, nz = 16, 12, 10
+    xf, yf, zf, flags, st = _empty_case(nx, ny, nz)
+    h = 1.0 / nx
+    k = (3, 2, 5)
+    i = np.arange(nx); j = np.arange(ny); kk = np.arange(nz)
+    vx = np.cos(np.pi * k[0] * (i + 0.5) / nx)
+    vy = np.cos(np.pi * k[1] * (j + 0.5) / ny)
+    vz = np.cos(np.pi * k[2] * (kk + 0.5) / nz)
+    v = (vz[:, None, None] * vy[None, :, None] * vx[None, None, :]).ravel()
+    lam = sum(4 * math.sin(math.pi * kd / (2 * nd)) ** 2 / h ** 2 for kd, nd in zip(k, (nx, ny, nz)))
+    beta = 4.0 / oracle.max_cell_scale(xf, yf, zf)
+    Hv = oracle.ad_apply(xf, yf, zf, flags, st, beta, v)
+    assert np.allclose(Hv, (1 + beta * lam) * v, rtol=0, atol=1e-12 * (1 + beta * lam))
+    om = oracle.ad_schedule(8, beta, oracle.max_cell_scale(xf, yf, zf))
+    u, cyc, rel, rc = oracle.ad_solve(xf, yf, zf, flags, st, beta, v, om, tol=1e-13)
+    assert rc == 0 and rel <= 1e-13
+    assert np.abs(u - v / (1 + beta * lam)).max() < 1e-12
+
+
+def test_dirichlet_rows_reproduce_linear_fields():
+    """A linear field u = a.x is reproduced exactly by the trilinear fit with
+    a value row at BI, so every non-fallback Dirichlet row holds
+    sG (sum w u + u_G) = sG (2 - beta_BI) a.BI, for closed ghosts and for
+    membrane ghost unknowns (the field is continuous across the sheet)."""
+    n = 32
+    f = W.uniform_faces(n)
+    bodies = [W.sphere((0.33, 0.5, 0.5), 0.17, freq=8),
+              W.plate((0.72, 0.5, 0.5), 0.2, 0.4, 10, 20, 0.04, 0.3)]
+    flags = oracle.classify(f, f, f, bodies)
+    st = oracle.stencils(f, f, f, bodies, flags, bc="dirichlet")
+    assert st.ng > 50 and st.nm > 50
+    c = W.centres(f)
+    a = np.array([0.8, -1.1, 1.7])
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    u = np.concatenate([(a[0] * X + a[1] * Y + a[2] * Z).ravel(), np.zeros(st.nm)])
+    u[n ** 3:] = u[st.mcell]
+    y = oracle.ad_apply(f, f, f, flags, st, 0.01, u)
+    rows = np.concatenate([st.gcell.astype(np.int64), n ** 3 + np.arange(st.nm)])
+    BI = st.geo[:, 0:3]
+    want = st.sG * st.dlb * (BI @ a)
+    ok = (st.rfl & 1) == 0
+    assert ok.sum() > 0.9 * len(ok)
+    err = np.abs(y[rows] - want)[ok]
+    assert err.max() <= 1e-11 * np.abs(st.sG).max()
+    # the Neumann rows of the same geometry are different rows: the sign of
+    # the ghost term and the BI row differ
+    stn = oracle.stencils(f, f, f, bodies, flags)
+    assert not np.allclose(stn.dlb, st.dlb)
+
+
+def test_ad_srj_solve_matches_direct_solve():
+    """With a sphere and a membrane on a 16^3 grid, the SRJ cycles converge
+    to the solution of the assembled sparse system (scipy)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    n = 16
+    f = W.uniform_faces(n)
+    bodies = [W.sphere((0.35, 0.5, 0.5), 0.2, freq=6), W.plate((0.75, 0.5, 0.5), 0.2, 0.5, 6, 12)]
+    flags = oracle.classify(f, f, f, bodies)
+    st = oracle.stencils(f, f, f, bodies, flags, bc="dirichlet")
+    N = n ** 3
+    nt = N + st.nm
+    beta = 3.0 / oracle.max_cell_scale(f, f, f)
+    active = np.ones(nt, bool)
+    active[:N] = ((flags & oracle.F_SOLID) == 0) | ((flags & oracle.F_GHOST) != 0)
+    idx = np.nonzero(active)[0]
+    cols = []
+    e = np.zeros(nt)
+    for q in idx:
+        e[q] = 1.0
+        cols.append(oracle.ad_apply(f, f, f, flags, st, beta, e)[idx])
+        e[q] = 0.0
+    H = sp.csc_matrix(np.array(cols).T)
+    rng = np.random.default_rng(9)
+    fr = rng.uniform(-1, 1, N)
+    g = rng.uniform(-0.5, 0.5, st.ng + st.nm)
+    rhs = oracle.ad_rhs(f, f, f, flags, st, fr, g)
+    want = np.zeros(nt)
+    want[idx] = spla.spsolve(H, rhs[idx])
+    for m in (4, 8, 16):
+        om = oracle.ad_schedule(m, beta, oracle.max_cell_scale(f, f, f))
+        u, cyc, rel, rc = oracle.ad_solve(f, f, f, flags, st, beta, rhs, om, tol=1e-13, maxcyc=2000)
+        assert rc == 0, (m, cyc, rel)
+        assert np.linalg.norm(u - want) <= 1e-10 * np.linalg.norm(want)
