@@ -155,6 +155,21 @@ int32_t ibm_classify(const ibm_grid *grid, const ibm_body *bodies, int32_t n_bod
 int32_t ibm_build_ghost_stencils(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body,
                                  const uint8_t *flags_dev, ibm_stencils **out, void *stream);
 
+/* Boundary condition of the ghost rows.  NEUMANN: the pressure rows above.
+ * DIRICHLET: rows of the advection-diffusion step, where the value at BI is
+ * the mean of the ghost and image-point values; when G is a node of the box
+ * a value row at BI replaces the derivative row, giving
+ * sG (sum w x + x_G) = sG (2 - beta_BI) g with dlb = 2 - beta_BI (a ghost on
+ * the surface gets x_G = g, dlb = 1; the first-order fallback uses the
+ * neighbour mean with dlb = 2). */
+#define IBM_BC_NEUMANN 0
+#define IBM_BC_DIRICHLET 1
+
+/* ibm_build_ghost_stencils with the boundary condition chosen (IBM_EINVAL
+ * for another value); ibm_build_ghost_stencils is the NEUMANN case. */
+int32_t ibm_build_ghost_stencils_bc(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body,
+                                    const uint8_t *flags_dev, int32_t bc, ibm_stencils **out, void *stream);
+
 /* Row counts of a stencil table (any pointer may be NULL). */
 int32_t ibm_stencils_info(const ibm_stencils *s, int64_t *n_ghost, int64_t *n_mghost, int64_t *n_fallback);
 
@@ -237,6 +252,52 @@ int32_t poisson_solve(poisson_ctx *ctx, const double *f_dev, const double *g_dev
  */
 int32_t ibm_surface_forces(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body, const uint8_t *flags_dev,
                            const double *p_dev, double *force_dev, double *dp_dev, int64_t *n_lost, void *stream);
+
+/*
+ * Advection-diffusion step (Sec. 2.1: the momentum equations of the
+ * fractional step are solved with scheduled relaxed Jacobi).  One velocity
+ * component: H u = u - beta L u on fluid cells, L the 7-point operator of the
+ * pressure system (zero-flux walls, the far side's ghost unknown across a cut
+ * membrane link), beta = nu dt (times 1/2 for Crank-Nicolson); Dirichlet
+ * ghost rows from ibm_build_ghost_stencils_bc(..., IBM_BC_DIRICHLET, ...);
+ * solid non-ghost unknowns are 0.  SRJ cycle: `sweeps` weighted Jacobi
+ * sweeps u <- u + omega_s D^-1 (rhs - H u), D = 1 + beta sum c (fluid) or sG
+ * (ghost rows), omega_s the reciprocals of the degree-`sweeps` Chebyshev
+ * roots on [a, 2 - a], a = 1 / (1 + beta max sum c); the relative residual
+ * ||rhs - H u|| / ||rhs|| is checked after every cycle.
+ */
+typedef struct ibm_ad_ctx ibm_ad_ctx; /* opaque, library-owned */
+
+typedef struct ibm_ad_opts {
+    double beta;         /* diffusion number nu dt (>= 0) */
+    double tol;          /* relative residual */
+    int32_t sweeps;      /* SRJ sweeps per cycle, 1..64 */
+    int32_t max_cycles;  /* cycle limit */
+} ibm_ad_opts;
+
+typedef struct ibm_ad_stats {
+    int32_t cycles, sweeps, status;
+    double rel_residual; /* final relative residual (device reduction order) */
+    double solve_ms;     /* device time of the solve */
+} ibm_ad_stats;
+
+/* Defaults: beta 0, tol 1e-10, 8 sweeps per cycle, 500 cycles. */
+void ibm_ad_default_opts(ibm_ad_opts *opts);
+/* Set-up from the classification (device uint8[N]) and a Dirichlet table
+ * (IBM_EINVAL for a Neumann one or another grid); copies what it needs. */
+int32_t ibm_ad_setup(const ibm_grid *grid, const uint8_t *flags_dev, const ibm_stencils *st, const ibm_ad_opts *opts,
+                     ibm_ad_ctx **out);
+/* y = H x, device double[N + n_mghost] each, natural order. */
+int32_t ibm_ad_apply(ibm_ad_ctx *ctx, const double *x_dev, double *y_dev, void *stream);
+/* Solve H u = rhs, rhs = f on fluid cells (device double[N]) and
+ * sG dlb g on ghost rows (g_dev: device double[n_ghost + n_mghost], the wall
+ * velocity at each row's BI; NULL for walls at rest).  u_dev
+ * (double[N + n_mghost]) holds the initial guess on entry and the solution on
+ * return.  Blocks until done; IBM_ENOCONV at the cycle limit (u holds the
+ * last iterate), IBM_EBREAKDOWN for a non-finite residual. */
+int32_t ibm_ad_solve(ibm_ad_ctx *ctx, const double *f_dev, const double *g_dev, double *u_dev, ibm_ad_stats *stats,
+                     void *stream);
+void ibm_ad_destroy(ibm_ad_ctx *ctx);
 
 /*
  * Moving bodies (the paper's time loop, Sec. 2.4 and 2.5: every step

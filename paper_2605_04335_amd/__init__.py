@@ -57,6 +57,19 @@ class PoissonOpts(ctypes.Structure):
                 ("precond", ctypes.c_int32), ("srj_sweeps", ctypes.c_int32)]
 
 
+BC_NEUMANN, BC_DIRICHLET = 0, 1
+
+
+class AdOpts(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("tol", ctypes.c_double), ("sweeps", ctypes.c_int32),
+                ("max_cycles", ctypes.c_int32)]
+
+
+class AdStats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+
+
 class PoissonStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("outer_steps", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("pin_residual", ctypes.c_double),
@@ -86,7 +99,9 @@ EXPORTS = ["ibm_classify", "ibm_build_ghost_stencils", "ibm_stencils_info", "ibm
            "poisson_solve", "poisson_apply", "poisson_assemble_rhs", "poisson_precond", "poisson_solve_assembled",
            "poisson_destroy", "poisson_workspace_size", "poisson_bind_workspace", "poisson_server_create",
            "poisson_submit", "poisson_poll", "poisson_server_drain", "poisson_server_destroy", "ibm_last_error",
-           "poisson_update", "poisson_solve_from", "ibm_fill_fresh", "ibm_surface_forces"]
+           "poisson_update", "poisson_solve_from", "ibm_fill_fresh", "ibm_surface_forces",
+           "ibm_build_ghost_stencils_bc", "ibm_ad_default_opts", "ibm_ad_setup", "ibm_ad_apply", "ibm_ad_solve",
+           "ibm_ad_destroy"]
 
 _lib = None
 
@@ -104,6 +119,9 @@ def lib():
         L.ibm_stencils_free.restype = None
         L.poisson_destroy.restype = None
         L.poisson_default_opts.restype = None
+        if hasattr(L, "ibm_ad_default_opts"):
+            L.ibm_ad_default_opts.restype = None
+            L.ibm_ad_destroy.restype = None
         if hasattr(L, "poisson_server_destroy"):
             L.poisson_server_destroy.restype = None
         _lib = L
@@ -242,13 +260,66 @@ class Stencils:
             pass
 
 
-def build_ghost_stencils(xf, yf, zf, bodies, flags) -> Stencils:
+def build_ghost_stencils(xf, yf, zf, bodies, flags, bc: str = "neumann") -> Stencils:
+    """Ghost rows: Neumann (pressure) or Dirichlet (advection-diffusion)."""
     G = _GridArgs(xf, yf, zf)
     B = _BodyArgs(bodies)
     h = ctypes.c_void_p()
-    _check(lib().ibm_build_ghost_stencils(ctypes.byref(G.g), B.arr, ctypes.c_int32(B.n), _tptr(flags),
-                                          ctypes.byref(h), _stream()), "ibm_build_ghost_stencils")
+    code = {"neumann": BC_NEUMANN, "dirichlet": BC_DIRICHLET}[bc]
+    _check(lib().ibm_build_ghost_stencils_bc(ctypes.byref(G.g), B.arr, ctypes.c_int32(B.n), _tptr(flags),
+                                             ctypes.c_int32(code), ctypes.byref(h), _stream()),
+           "ibm_build_ghost_stencils_bc")
     return Stencils(h, G.N)
+
+
+# ------------------------------------------------------------------ advection-diffusion step
+class AdSolver:
+    """An ibm_ad_ctx: H u = u - beta L u with Dirichlet ghost rows, solved by SRJ cycles."""
+
+    def __init__(self, xf, yf, zf, flags, stencils: "Stencils", beta: float, tol: float = 1e-10, sweeps: int = 8,
+                 max_cycles: int = 500):
+        self.G = _GridArgs(xf, yf, zf)
+        o = AdOpts()
+        lib().ibm_ad_default_opts(ctypes.byref(o))
+        o.beta, o.tol, o.sweeps, o.max_cycles = beta, tol, sweeps, max_cycles
+        self.opts = o
+        ng, nm, nf = stencils.info()
+        self.N, self.nm, self.ng = self.G.N, nm, ng
+        self.h = ctypes.c_void_p()
+        _check(lib().ibm_ad_setup(ctypes.byref(self.G.g), _tptr(flags), stencils.h, ctypes.byref(o),
+                                  ctypes.byref(self.h)), "ibm_ad_setup")
+
+    def _vec(self, device="cuda"):
+        import torch
+        return torch.zeros(self.N + self.nm, dtype=torch.float64, device=device)
+
+    def apply(self, x, y=None):
+        if y is None:
+            y = self._vec(x.device)
+        _check(lib().ibm_ad_apply(self.h, _tptr(x), _tptr(y), _stream()), "ibm_ad_apply")
+        return y
+
+    def solve(self, f, g=None, u=None, check=True):
+        """u (device double[N + n_mghost]) is the initial guess and receives the solution."""
+        if u is None:
+            u = self._vec(f.device)
+        st = AdStats()
+        rc = lib().ibm_ad_solve(self.h, _tptr(f), _tptr(g) if g is not None else None, _tptr(u), ctypes.byref(st),
+                                _stream())
+        if check:
+            _check(rc, "ibm_ad_solve")
+        return u, st
+
+    def close(self):
+        if self.h:
+            lib().ibm_ad_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ solver

@@ -2,7 +2,8 @@
 
 Every translation unit is compiled for gfx950 only with packed-FP32
 instructions disabled; the classification, ghost-stencil and surface-load
-units are compiled without FMA contraction so their quantisation,
+and advection-diffusion units are compiled without FMA contraction so their
+quantisation,
 predicates, distance comparisons and interpolations round exactly as
 written.
 """
@@ -26,6 +27,7 @@ UNITS = {
     "solver.hip": [],
     "server.hip": [],
     "forces.hip": ["-ffp-contract=off"],
+    "ad.hip": ["-ffp-contract=off"],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

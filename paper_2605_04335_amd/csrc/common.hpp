@@ -153,6 +153,7 @@ struct ibm_stencils {
     int n[3] = {0, 0, 0};
     int64_t N = 0;
     int64_t ng = 0, nm = 0, nfallback = 0, pin = -1;
+    int bc = 0;                // IBM_BC_NEUMANN or IBM_BC_DIRICHLET rows
     ibm::DBuf<int32_t> cell;   // [ng + nm] closed ghost cells then membrane ghost cells (sorted)
     ibm::DBuf<int32_t> col;    // [rows*8]
     ibm::DBuf<double> w;       // [rows*8]

@@ -23,7 +23,8 @@
 
 namespace ibm {
 void classify(const ibm_grid *, const ibm_body *, int, uint8_t *, ibm_class_stats *, hipStream_t);
-void build_stencils(const ibm_grid *, const ibm_body *, int, const uint8_t *, ibm_stencils **, hipStream_t);
+void build_stencils(const ibm_grid *, const ibm_body *, int, const uint8_t *, ibm_stencils **, hipStream_t,
+                    int bc = 0);
 size_t estimate_bytes(int nx, int ny, int nz, long long nrows, int precision);
 }  // namespace ibm
 

@@ -191,7 +191,8 @@ struct RowOut {
 
 // One thread per ghost row: intercept, image point, box, 8x8 LU, weights.
 __global__ void __launch_bounds__(64) k_stencil(Tris T, GridD G, const uint8_t *flags, const int32_t *cells,
-                                                int ng, int nrows, const int32_t *mcell, int nm, long long N, RowOut O)
+                                                int ng, int nrows, const int32_t *mcell, int nm, long long N, int bc,
+                                                RowOut O)
 {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrows) return;
@@ -264,7 +265,13 @@ __global__ void __launch_bounds__(64) k_stencil(Tris T, GridD G, const uint8_t *
         const uint8_t f = flags[id];
         cl[m] = -1;
         double row[8];
-        if (id == cell) {
+        if (id == cell && bc == 1) {
+            // Dirichlet: value row at BI
+            const double x = bil[0], y = bil[1], z = bil[2];
+            row[0] = 1.0; row[1] = x; row[2] = y; row[3] = z;
+            row[4] = x * y; row[5] = y * z; row[6] = x * z; row[7] = x * y * z;
+            dnode = m;
+        } else if (id == cell) {
             const double x = bil[0], y = bil[1], z = bil[2];
             const double gx[8] = {0, 1, 0, 0, y, 0, z, y * z};
             const double gy[8] = {0, 0, 1, 0, x, z, 0, x * z};
@@ -332,7 +339,12 @@ __global__ void __launch_bounds__(64) k_stencil(Tris T, GridD G, const uint8_t *
             ow[m] = cl[m] >= 0 ? beta[m] : 0.0;
         }
         if (dnode >= 0) { bbi = beta[dnode]; fl |= 2; }
-        O.dlb[r] = dl - bbi;
+        O.dlb[r] = bc == 1 ? 2.0 - bbi : dl - bbi;
+        if (bc == 1 && (fl & 4)) {
+            // ghost on the surface: x_G = g
+            for (int m = 0; m < 8; ++m) { oc[m] = -1; ow[m] = 0.0; }
+            O.dlb[r] = 1.0;
+        }
     } else {
         fl |= 1;
         int cnt = 0;
@@ -351,7 +363,7 @@ __global__ void __launch_bounds__(64) k_stencil(Tris T, GridD G, const uint8_t *
             }
         for (int m = 0; m < 8; ++m) { oc[m] = -1; ow[m] = 0.0; }
         for (int m = 0; m < cnt; ++m) { oc[m] = nb[m]; ow[m] = 1.0 / cnt; }
-        O.dlb[r] = 0.0;
+        O.dlb[r] = bc == 1 ? 2.0 : 0.0;
     }
     O.sG[r] = sg;
     O.rfl[r] = fl;
@@ -391,8 +403,9 @@ int64_t compact_cells(const uint8_t *flags, long long N, uint8_t mask, DBuf<int3
 }
 
 void build_stencils(const ibm_grid *grid, const ibm_body *bodies, int n_body, const uint8_t *flags, ibm_stencils **out,
-                    hipStream_t s)
+                    hipStream_t s, int bc = 0)
 {
+    IBM_REQUIRE(bc == IBM_BC_NEUMANN || bc == IBM_BC_DIRICHLET, IBM_EINVAL, "unknown boundary condition");
     HostGrid g = read_grid(grid);
     IBM_REQUIRE(flags && out, IBM_EINVAL, "null argument");
     IBM_REQUIRE(n_body >= 0 && (n_body == 0 || bodies), IBM_EINVAL, "bad body list");
@@ -401,6 +414,7 @@ void build_stencils(const ibm_grid *grid, const ibm_body *bodies, int n_body, co
     try {
         for (int d = 0; d < 3; ++d) S->n[d] = g.n[d];
         S->N = N;
+        S->bc = bc;
         DBuf<int32_t> gl, ml;
         S->ng = compact_cells(flags, N, F_GHOST, gl, s);
         S->nm = compact_cells(flags, N, F_MGHOST, ml, s);
@@ -484,7 +498,7 @@ void build_stencils(const ibm_grid *grid, const ibm_body *bodies, int n_body, co
             Tris T{dtv.p, dtb.p, dtk.p, dbb.p, dbf.p, dbk.p, n_body};
             RowOut O{S->col.p, S->w.p, S->sG.p, S->dlb.p, S->geo.p, S->rfl.p};
             k_stencil<<<cdiv(rows, 64), 64, 0, s>>>(T, G, flags, S->cell.p, (int)S->ng, (int)rows, S->cell.p + S->ng,
-                                                   (int)S->nm, N, O);
+                                                   (int)S->nm, N, bc, O);
             IBM_LAUNCH_CHECK();
             DBuf<int> nf(1);
             IBM_HIP(hipMemsetAsync(nf.p, 0, 4, s));
@@ -508,6 +522,13 @@ extern "C" int32_t ibm_build_ghost_stencils(const ibm_grid *grid, const ibm_body
                                             const uint8_t *flags_dev, ibm_stencils **out, void *stream)
 {
     return ibm::guarded([&] { ibm::build_stencils(grid, bodies, n_body, flags_dev, out, (hipStream_t)stream); });
+}
+
+extern "C" int32_t ibm_build_ghost_stencils_bc(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body,
+                                               const uint8_t *flags_dev, int32_t bc, ibm_stencils **out, void *stream)
+{
+    return ibm::guarded(
+        [&] { ibm::build_stencils(grid, bodies, n_body, flags_dev, out, (hipStream_t)stream, bc); });
 }
 
 extern "C" int32_t ibm_stencils_info(const ibm_stencils *s, int64_t *n_ghost, int64_t *n_mghost, int64_t *n_fallback)
