@@ -191,6 +191,56 @@ def moving_bench(P, n=512, steps=3):
             "ok": sum(r["ok"] for r in rows)}
 
 
+def max_diag(xf, yf, zf):
+    """Largest sum of the 7-point coefficients of a cell (zero-flux walls)."""
+    tot = 0.0
+    for f in (xf, yf, zf):
+        c = 0.5 * (f[1:] + f[:-1])
+        w = np.diff(f)
+        d = np.zeros(len(w))
+        d[:-1] += 1.0 / (w[:-1] * np.diff(c))
+        d[1:] += 1.0 / (w[1:] * np.diff(c))
+        tot += d.max()
+    return float(tot)
+
+
+def ad_bench(P, n=512, components=3):
+    """Advection-diffusion step of the momentum equations (SRJ, Dirichlet
+    ghost rows) on the moving-body geometry: beta = nu dt / 2 at Re 1000 and
+    CFL 0.5 on the finest cell, one solve per velocity component to 1e-10."""
+    import torch
+    from paper_2605_04335_amd import workloads as W
+    p = W.flapping_case(n, 0, rhs=False)
+    flags, _ = P.classify(p.xf, p.yf, p.zf, p.bodies)
+    st = P.build_ghost_stencils(p.xf, p.yf, p.zf, p.bodies, flags, bc="dirichlet")
+    h = min(np.diff(p.xf).min(), np.diff(p.yf).min(), np.diff(p.zf).min())
+    beta = 0.5 * 1e-3 * 0.5 * h
+    sol = P.AdSolver(p.xf, p.yf, p.zf, flags, st, beta, tol=1e-10, sweeps=8)
+    ng, nm, _ = st.info()
+    rows = []
+    for c in range(components + 1):
+        f = torch.from_numpy(W.noise_rhs(p.npts, 70 + c)).cuda()
+        g = torch.from_numpy(np.random.default_rng(80 + c).uniform(-0.5, 0.5, ng + nm)).cuda()
+        u, s = sol.solve(f, g)
+        if c:  # the first solve is a warm-up
+            rows.append((s.solve_ms, s.cycles, s.sweeps, s.status, s.rel_residual))
+    del sol
+    torch.cuda.empty_cache()
+    ms = float(np.mean([r[0] for r in rows]))
+    sweeps = float(np.mean([r[2] for r in rows]))
+    cycles = float(np.mean([r[1] for r in rows]))
+    # a sweep reads x, rhs and flags and writes x (FP64): 25 bytes per cell;
+    # the residual after each cycle is one more pass of the same kind
+    passes = sweeps + cycles + 1
+    log("ad: %.1f ms per component, %.0f cycles, %.0f sweeps" % (ms, cycles, sweeps))
+    return {"workload": "u - beta L u = f per velocity component, flapping plate + heaving sphere, %d^3 "
+                        "tanh-stretched, Dirichlet ghost rows, beta = nu dt / 2 (Re 1000, CFL 0.5), SRJ to 1e-10" % n,
+            "ms_per_component": round(ms, 2), "cycles": cycles, "sweeps": sweeps,
+            "beta": beta, "beta_times_max_diag": round(beta * max_diag(p.xf, p.yf, p.zf), 3),
+            "GB_s_per_pass": round(25.0 * p.npts * passes / (ms * 1e-3) / 1e9, 1),
+            "ok": sum(1 for r in rows if r[3] == 0 and r[4] <= 1e-10), "components": components}
+
+
 def cpu_baseline(cfg, budget_s):
     """The FP64 oracle on a bounded sample of the same workload recipe."""
     import oracle
@@ -227,6 +277,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-moving", action="store_true", help="skip the moving-body time-step measurement")
+    ap.add_argument("--no-ad", action="store_true", help="skip the advection-diffusion step measurement")
     ap.add_argument("--serve-rates", default="5,20,80", help="request arrival rates (req/s) of the serving sweep")
     ap.add_argument("--serve-requests", type=int, default=24, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -333,6 +384,8 @@ def main():
         out["serving"] = serving_bench(P, [float(r) for r in args.serve_rates.split(",")], args.serve_requests)
     if not args.no_moving:
         out["moving"] = moving_bench(P)
+    if not args.no_ad:
+        out["advection_diffusion"] = ad_bench(P)
     if args.copy_calibration:
         import torch as _t
         nbytes = 1 << 30
