@@ -229,15 +229,15 @@ def ad_bench(P, n=512, components=3):
     ms = float(np.mean([r[0] for r in rows]))
     sweeps = float(np.mean([r[2] for r in rows]))
     cycles = float(np.mean([r[1] for r in rows]))
-    # a sweep reads x, rhs and flags and writes x (FP64): 25 bytes per cell;
-    # the residual after each cycle is one more pass of the same kind
-    passes = sweeps + cycles + 1
+    # a sweep reads the iterate, the right-hand side and the flags and writes
+    # the new iterate (FP64): 25 bytes per cell; the residual before the first
+    # and after every cycle reads the same without writing: 17 bytes per cell
     log("ad: %.1f ms per component, %.0f cycles, %.0f sweeps" % (ms, cycles, sweeps))
     return {"workload": "u - beta L u = f per velocity component, flapping plate + heaving sphere, %d^3 "
                         "tanh-stretched, Dirichlet ghost rows, beta = nu dt / 2 (Re 1000, CFL 0.5), SRJ to 1e-10" % n,
             "ms_per_component": round(ms, 2), "cycles": cycles, "sweeps": sweeps,
             "beta": beta, "beta_times_max_diag": round(beta * max_diag(p.xf, p.yf, p.zf), 3),
-            "GB_s_per_pass": round(25.0 * p.npts * passes / (ms * 1e-3) / 1e9, 1),
+            "GB_s": round(p.npts * (25.0 * sweeps + 17.0 * (cycles + 1)) / (ms * 1e-3) / 1e9, 1),
             "ok": sum(1 for r in rows if r[3] == 0 and r[4] <= 1e-10), "components": components}
 
 

@@ -48,24 +48,6 @@ __device__ __forceinline__ long long row_unknown(const AdRows &R, const AdGrid &
     return r < R.ng ? (long long)R.rcell[r] : G.N + (r - R.ng);
 }
 
-// (H x)[p] for a regular fluid cell (no cut link): the order of the
-// definition, sum over +x, -x, +y, -y, +z, -z of c (x_nb - x_p)
-__device__ __forceinline__ double h_regular(const AdGrid &G, double beta, const double *x, long long p, int i, int j,
-                                            int k, double &dg)
-{
-    const double xp = x[p];
-    const long long sd[3] = {1, G.nx, (long long)G.nx * G.ny};
-    const int ci[3] = {i, j, k}, nd[3] = {G.nx, G.ny, G.nz};
-    double acc = 0.0;
-    dg = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        if (ci[d] + 1 < nd[d]) acc += G.cp[d][ci[d]] * (x[p + sd[d]] - xp);
-        if (ci[d] > 0) acc += G.cm[d][ci[d]] * (x[p - sd[d]] - xp);
-    }
-    dg = G.cp[0][i] + G.cm[0][i] + G.cp[1][j] + G.cm[1][j] + G.cp[2][k] + G.cm[2][k];
-    return xp - beta * acc;
-}
-
 // membrane cell: neighbours from its six columns (ghost unknowns across cut links)
 __device__ __forceinline__ double h_membrane(const AdGrid &G, const AdRows &R, double beta, const double *x, int m,
                                              double &dg)
@@ -94,62 +76,125 @@ __device__ __forceinline__ double h_ghost(const AdGrid &G, const AdRows &R, cons
     return R.sG[r] * (acc + x[u]);
 }
 
-// Jacobi sweep (JAC) or y = H x on the regular cells; one block per (row j, plane k)
-template <bool JAC>
-__global__ void __launch_bounds__(ATPB) k_ad_dense(AdGrid G, const uint8_t *__restrict__ flags, double beta,
-                                                   double omega, const double *__restrict__ x, double *__restrict__ y,
-                                                   const double *__restrict__ rhs)
+// Jacobi sweep (JAC) or y = H x on the regular cells.  A 64 x 4 block
+// covers (i, j) of a tile and each thread walks KZ planes, keeping the
+// iterate of planes k-1, k, k+1 in registers (each plane is loaded once).
+// Tiles are remapped so that each XCD owns a contiguous range (its own L2).
+constexpr int AD_KZ = 16;
+enum { AD_APPLY = 0, AD_JACOBI = 1, AD_RESID = 2 };
+
+// block sums of a and b into part[2 blk], part[2 blk + 1] (fixed order)
+__device__ __forceinline__ void ad_block_sums(double a, double b, double *part)
 {
-    const int j = blockIdx.x, k = blockIdx.y;
-    for (int i = threadIdx.x; i < G.nx; i += ATPB) {
-        const long long p = (long long)i + (long long)G.nx * (j + (long long)G.ny * k);
-        const uint8_t f = flags[p];
-        if (f & F_SOLID) {
-            if (!(f & F_GHOST)) y[p] = 0.0;  // ghost rows: the sparse kernel
-            continue;
-        }
-        if (f & F_MGHOST) continue;  // cells with cut links: the sparse kernel
-        double dg;
-        const double hx = h_regular(G, beta, x, p, i, j, k, dg);
-        if (JAC) {
-            const double dinv = 1.0 / (1.0 + beta * dg);
-            y[p] = x[p] + omega * dinv * (rhs[p] - hx);
-        } else {
-            y[p] = hx;
+    __shared__ double s0[ATPB / 64], s1[ATPB / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        b += __shfl_down(b, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) { s0[wv] = a; s1[wv] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+        for (int q = 0; q < ATPB / 64; ++q) { ta += s0[q]; tb += s1[q]; }
+        part[2 * blockIdx.x] = ta;
+        part[2 * blockIdx.x + 1] = tb;
+    }
+}
+struct AdTiles {
+    int gx, gy, gz, per;
+};
+// MODE: y = H x (AD_APPLY), a Jacobi sweep into y (AD_JACOBI), or per-block
+// sums of (rhs - H x)^2 and rhs^2 into part (AD_RESID, nothing written)
+template <int MODE>
+__global__ void __launch_bounds__(ATPB) k_ad_dense(AdGrid G, AdTiles T, const uint8_t *__restrict__ flags, double beta,
+                                                   double omega, const double *__restrict__ x, double *__restrict__ y,
+                                                   const double *__restrict__ rhs, double *part)
+{
+    const int t = (int)(blockIdx.x & 7) * T.per + (int)(blockIdx.x >> 3);
+    const int tx = t % T.gx, ty = (t / T.gx) % T.gy, tz = t / (T.gx * T.gy);
+    const int i = tx * 64 + (int)(threadIdx.x & 63), j = ty * 4 + (int)(threadIdx.x >> 6);
+    double ra = 0.0, rb = 0.0;
+    if (t < T.gx * T.gy * T.gz && i < G.nx && j < G.ny) {
+        const int k0 = tz * AD_KZ, k1 = min(k0 + AD_KZ, G.nz);
+        const long long pl = (long long)G.nx * G.ny;
+        long long p = (long long)i + (long long)G.nx * (j + (long long)G.ny * k0);
+        const double cpx = G.cp[0][i], cmx = G.cm[0][i], cpy = G.cp[1][j], cmy = G.cm[1][j];
+        const bool hx_p = i + 1 < G.nx, hx_m = i > 0, hy_p = j + 1 < G.ny, hy_m = j > 0;
+        double xm = k0 > 0 ? x[p - pl] : 0.0, xc = x[p];
+        for (int k = k0; k < k1; ++k, p += pl) {
+            const double xn = k + 1 < G.nz ? x[p + pl] : 0.0;
+            const uint8_t f = flags[p];
+            const double vxp = hx_p ? x[p + 1] : 0.0, vxm = hx_m ? x[p - 1] : 0.0;
+            const double vyp = hy_p ? x[p + G.nx] : 0.0, vym = hy_m ? x[p - G.nx] : 0.0;
+            const double bv = MODE != AD_APPLY ? rhs[p] : 0.0;
+            if (f & F_SOLID) {
+                if (!(f & F_GHOST)) {  // ghost rows: the sparse kernel
+                    if (MODE == AD_RESID) { ra += bv * bv; rb += bv * bv; }
+                    else y[p] = 0.0;
+                }
+            } else if (!(f & F_MGHOST)) {  // cells with cut links: the sparse kernel
+                // the order of the definition: +x, -x, +y, -y, +z, -z
+                double acc = 0.0;
+                if (hx_p) acc += cpx * (vxp - xc);
+                if (hx_m) acc += cmx * (vxm - xc);
+                if (hy_p) acc += cpy * (vyp - xc);
+                if (hy_m) acc += cmy * (vym - xc);
+                if (k + 1 < G.nz) acc += G.cp[2][k] * (xn - xc);
+                if (k > 0) acc += G.cm[2][k] * (xm - xc);
+                const double hx = xc - beta * acc;
+                if (MODE == AD_JACOBI) {
+                    const double dg = cpx + cmx + cpy + cmy + G.cp[2][k] + G.cm[2][k];
+                    const double dinv = 1.0 / (1.0 + beta * dg);
+                    y[p] = xc + omega * dinv * (bv - hx);
+                } else if (MODE == AD_RESID) {
+                    const double r = bv - hx;
+                    ra += r * r;
+                    rb += bv * bv;
+                } else {
+                    y[p] = hx;
+                }
+            }
+            xm = xc;
+            xc = xn;
         }
     }
+    if (MODE == AD_RESID) ad_block_sums(ra, rb, part);
 }
 
 // the same for ghost rows (r < nrows) and membrane cells (nrows + m)
-template <bool JAC>
+template <int MODE>
 __global__ void __launch_bounds__(ATPB) k_ad_sparse(AdGrid G, AdRows R, double beta, double omega,
                                                     const double *__restrict__ x, double *__restrict__ y,
-                                                    const double *__restrict__ rhs)
+                                                    const double *__restrict__ rhs, double *part)
 {
     const int n = R.nrows + R.nm;
+    double ra = 0.0, rb = 0.0;
     for (int q = blockIdx.x * ATPB + threadIdx.x; q < n; q += gridDim.x * ATPB) {
+        long long u;
+        double hx, dinv;
         if (q < R.nrows) {
-            const long long u = row_unknown(R, G, q);
-            const double hx = h_ghost(G, R, x, q, u);
-            if (JAC) {
-                const double dinv = 1.0 / R.sG[q];
-                y[u] = x[u] + omega * dinv * (rhs[u] - hx);
-            } else {
-                y[u] = hx;
-            }
+            u = row_unknown(R, G, q);
+            hx = h_ghost(G, R, x, q, u);
+            dinv = 1.0 / R.sG[q];
         } else {
             const int m = q - R.nrows;
-            const long long p = R.mcell[m];
+            u = R.mcell[m];
             double dg;
-            const double hx = h_membrane(G, R, beta, x, m, dg);
-            if (JAC) {
-                const double dinv = 1.0 / (1.0 + beta * dg);
-                y[p] = x[p] + omega * dinv * (rhs[p] - hx);
-            } else {
-                y[p] = hx;
-            }
+            hx = h_membrane(G, R, beta, x, m, dg);
+            dinv = 1.0 / (1.0 + beta * dg);
+        }
+        if (MODE == AD_JACOBI) {
+            y[u] = x[u] + omega * dinv * (rhs[u] - hx);
+        } else if (MODE == AD_RESID) {
+            const double r = rhs[u] - hx;
+            ra += r * r;
+            rb += rhs[u] * rhs[u];
+        } else {
+            y[u] = hx;
         }
     }
+    if (MODE == AD_RESID) ad_block_sums(ra, rb, part);
 }
 
 // right-hand side: f on fluid cells, 0 on solid cells, sG dlb g on ghost rows
@@ -171,32 +216,6 @@ __global__ void __launch_bounds__(ATPB) k_ad_zero_solid(AdGrid G, const uint8_t 
 {
     for (long long p = blockIdx.x * (long long)ATPB + threadIdx.x; p < G.N; p += (long long)gridDim.x * ATPB)
         if ((flags[p] & F_SOLID) && !(flags[p] & F_GHOST)) x[p] = 0.0;
-}
-
-// per-block partial sums of (rhs - y)^2 and rhs^2 over n unknowns
-__global__ void __launch_bounds__(ATPB) k_ad_norms(long long n, const double *__restrict__ rhs,
-                                                   const double *__restrict__ y, double *part)
-{
-    __shared__ double s0[ATPB / 64], s1[ATPB / 64];
-    double a = 0.0, b = 0.0;
-    for (long long q = blockIdx.x * (long long)ATPB + threadIdx.x; q < n; q += (long long)gridDim.x * ATPB) {
-        const double r = rhs[q] - y[q];
-        a += r * r;
-        b += rhs[q] * rhs[q];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_down(a, o, 64);
-        b += __shfl_down(b, o, 64);
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) { s0[wv] = a; s1[wv] = b; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double ta = 0.0, tb = 0.0;
-        for (int q = 0; q < ATPB / 64; ++q) { ta += s0[q]; tb += s1[q]; }
-        part[2 * blockIdx.x] = ta;
-        part[2 * blockIdx.x + 1] = tb;
-    }
 }
 
 // membrane cells: the unknown behind each face (natural numbering)
@@ -264,7 +283,6 @@ struct ibm_ad_ctx {
 
 namespace {
 
-constexpr int AD_NB = 1024;  // blocks of the norm reduction
 
 struct AdJoin {
     ibm_ad_ctx &c;
@@ -297,31 +315,50 @@ std::vector<double> ad_schedule(int m, double beta, double dg_max)
 
 int sparse_blocks_ad(long long n) { return (int)std::min<long long>(std::max<long long>((n + ATPB - 1) / ATPB, 1), 4096); }
 
+AdTiles ad_tiles(const AdGrid &G)
+{
+    AdTiles T;
+    T.gx = (G.nx + 63) / 64;
+    T.gy = (G.ny + 3) / 4;
+    T.gz = (G.nz + AD_KZ - 1) / AD_KZ;
+    T.per = (T.gx * T.gy * T.gz + 7) / 8;
+    return T;
+}
+
 void ad_operator(ibm_ad_ctx &c, bool jac, double omega, const double *x, double *y, hipStream_t s)
 {
-    dim3 grid(c.G.ny, c.G.nz);
-    const int ns = c.R.nrows + c.R.nm;
+    const AdTiles T = ad_tiles(c.G);
+    const int grid = 8 * T.per, ns = c.R.nrows + c.R.nm;
     if (jac) {
-        k_ad_dense<true><<<grid, ATPB, 0, s>>>(c.G, c.flags.p, c.opts.beta, omega, x, y, c.rhs.p);
-        if (ns) k_ad_sparse<true><<<sparse_blocks_ad(ns), ATPB, 0, s>>>(c.G, c.R, c.opts.beta, omega, x, y, c.rhs.p);
+        k_ad_dense<AD_JACOBI><<<grid, ATPB, 0, s>>>(c.G, T, c.flags.p, c.opts.beta, omega, x, y, c.rhs.p, nullptr);
+        if (ns)
+            k_ad_sparse<AD_JACOBI><<<sparse_blocks_ad(ns), ATPB, 0, s>>>(c.G, c.R, c.opts.beta, omega, x, y, c.rhs.p,
+                                                                         nullptr);
     } else {
-        k_ad_dense<false><<<grid, ATPB, 0, s>>>(c.G, c.flags.p, c.opts.beta, 0.0, x, y, nullptr);
-        if (ns) k_ad_sparse<false><<<sparse_blocks_ad(ns), ATPB, 0, s>>>(c.G, c.R, c.opts.beta, 0.0, x, y, nullptr);
+        k_ad_dense<AD_APPLY><<<grid, ATPB, 0, s>>>(c.G, T, c.flags.p, c.opts.beta, 0.0, x, y, nullptr, nullptr);
+        if (ns)
+            k_ad_sparse<AD_APPLY><<<sparse_blocks_ad(ns), ATPB, 0, s>>>(c.G, c.R, c.opts.beta, 0.0, x, y, nullptr,
+                                                                        nullptr);
     }
     IBM_LAUNCH_CHECK();
 }
 
-// relative residual ||rhs - H x|| / ||rhs|| (y: scratch)
-double ad_residual(ibm_ad_ctx &c, const double *x, double *y, hipStream_t s)
+// relative residual ||rhs - H x|| / ||rhs||: block sums of the dense and the
+// sparse rows, added on the host in block order
+double ad_residual(ibm_ad_ctx &c, const double *x, hipStream_t s)
 {
-    ad_operator(c, false, 0.0, x, y, s);
-    k_ad_norms<<<AD_NB, ATPB, 0, s>>>(c.Nt, c.rhs.p, y, c.part.p);
+    const AdTiles T = ad_tiles(c.G);
+    const int grid = 8 * T.per, ns = c.R.nrows + c.R.nm, gs = ns ? sparse_blocks_ad(ns) : 0;
+    k_ad_dense<AD_RESID><<<grid, ATPB, 0, s>>>(c.G, T, c.flags.p, c.opts.beta, 0.0, x, nullptr, c.rhs.p, c.part.p);
+    if (ns)
+        k_ad_sparse<AD_RESID><<<gs, ATPB, 0, s>>>(c.G, c.R, c.opts.beta, 0.0, x, nullptr, c.rhs.p,
+                                                  c.part.p + 2 * (size_t)grid);
     IBM_LAUNCH_CHECK();
-    std::vector<double> h(2 * AD_NB);
+    std::vector<double> h(2 * (size_t)(grid + gs));
     IBM_HIP(hipMemcpyAsync(h.data(), c.part.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     IBM_HIP(hipStreamSynchronize(s));
     double a = 0.0, b = 0.0;
-    for (int q = 0; q < AD_NB; ++q) { a += h[2 * q]; b += h[2 * q + 1]; }
+    for (size_t q = 0; q < h.size() / 2; ++q) { a += h[2 * q]; b += h[2 * q + 1]; }
     return b > 0.0 ? std::sqrt(a / b) : std::sqrt(a);
 }
 
@@ -407,7 +444,7 @@ extern "C" int32_t ibm_ad_setup(const ibm_grid *grid, const uint8_t *flags_dev, 
         c->rhs.alloc(c->Nt);
         c->xa.alloc(c->Nt);
         c->xb.alloc(c->Nt);
-        c->part.alloc(2 * AD_NB);
+        c->part.alloc(2 * ((size_t)8 * ad_tiles(G).per + 4096));
         IBM_HIP(hipStreamSynchronize(s));
         IBM_REQUIRE(herr == 0, IBM_EGEOM, "cut link without ghost");
         *out = c.release();
@@ -439,7 +476,7 @@ extern "C" int32_t ibm_ad_solve(ibm_ad_ctx *c, const double *f_dev, const double
         IBM_HIP(hipMemcpyAsync(c->xb.p, c->xa.p, Nt * sizeof(double), hipMemcpyDeviceToDevice, s));
         IBM_LAUNCH_CHECK();
         double *x = c->xa.p, *y = c->xb.p;
-        double rel = ad_residual(*c, x, y, s);
+        double rel = ad_residual(*c, x, s);
         int cyc = 0, rc = rel <= c->opts.tol ? IBM_OK : IBM_ENOCONV;
         const int m = (int)c->omega.size();
         while (rc != IBM_OK && cyc < c->opts.max_cycles) {
@@ -448,7 +485,7 @@ extern "C" int32_t ibm_ad_solve(ibm_ad_ctx *c, const double *f_dev, const double
                 std::swap(x, y);
             }
             ++cyc;
-            rel = ad_residual(*c, x, y, s);
+            rel = ad_residual(*c, x, s);
             if (!std::isfinite(rel)) { rc = IBM_EBREAKDOWN; break; }
             if (rel <= c->opts.tol) rc = IBM_OK;
         }
