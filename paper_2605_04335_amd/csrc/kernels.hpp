@@ -480,8 +480,11 @@ __global__ void __launch_bounds__(TPB) k_csweep(Lv L, Geo G, T *__restrict__ x, 
 }
 
 // Level-0 Gauss-Seidel half-sweep of colour c (ordinary mode): xc, bc, fc
-// are this colour's arrays, xo the other colour's.  Four planes per step,
-// all loads issued before any store.  pin_s: the pin's slot within this
+// are this colour's arrays, xo the other colour's.  The other colour's slot
+// at the same (h, j, k) is an x neighbour of the cell in plane k and its z
+// neighbour in planes k-1 and k+1, so on FP64 levels each thread walks its
+// planes with a three-plane window of those values in registers; four
+// planes per step, all loads issued before any store.  pin_s: the pin's slot within this
 // colour (or -1), whose RHS carries the sink.
 constexpr int U0 = 4;
 template <class T>
@@ -494,25 +497,70 @@ __global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T 
     const Col0 q = col0(L, c, h, j);
     const long long pl = (long long)L.H * L.ny;
     const long long col = h + (long long)L.H * j;
+    if constexpr (!std::is_same<T, double>::value) {
+        // FP32 levels: every neighbour loaded per plane measured faster here
+        for (int kb = k0; kb < k1; kb += U0) {
+            double nb[U0], bb[U0], dg[U0];
+            uint8_t fl[U0];
+#pragma unroll
+            for (int u = 0; u < U0; ++u) {
+                const int k = min(kb + u, k1 - 1);
+                const long long s = col + pl * k;
+                fl[u] = fc[s];
+                bb[u] = ld(bc, s);
+                nb[u] = col0_sum(L, q, xo, s, k, pl, dg[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U0; ++u) {
+                const long long s = col + pl * (kb + u);
+                if (kb + u >= k1 || (fl[u] & (F_SOLID | F_MGHOST))) continue;
+                double b0 = bb[u];
+                if (s == pin_s) b0 -= sink[0];
+                st(xc, s, (nb[u] - b0) / dg[u]);
+            }
+        }
+        return;
+    }
+    // centres of planes k-1 and k (zero coefficient outside the grid)
+    double cprev = k0 > 0 ? ld(xo, col + pl * (k0 - 1)) : 0.0;
+    double ccur = ld(xo, col + pl * k0);
     for (int kb = k0; kb < k1; kb += U0) {
-        double nb[U0], bb[U0], dg[U0];
+        double cn[U0], xs[U0], yp[U0], ym[U0], bb[U0];
         uint8_t fl[U0];
 #pragma unroll
         for (int u = 0; u < U0; ++u) {
             const int k = min(kb + u, k1 - 1);
             const long long s = col + pl * k;
+            const bool t = k & 1;
+            const int o = t ? q.oxp[1] + q.oxm[1] : q.oxp[0] + q.oxm[0];  // the x neighbour that is not the centre
+            cn[u] = k + 1 < L.nz ? ld(xo, s + pl) : 0.0;                   // centre of plane k+1
+            xs[u] = ld(xo, s + o);
+            yp[u] = ld(xo, s + q.oyp);
+            ym[u] = ld(xo, s + q.oym);
             fl[u] = fc[s];
             bb[u] = ld(bc, s);
-            nb[u] = col0_sum(L, q, xo, s, k, pl, dg[u]);
         }
 #pragma unroll
         for (int u = 0; u < U0; ++u) {
-            const long long s = col + pl * (kb + u);
-            if (kb + u >= k1 || (fl[u] & (F_SOLID | F_MGHOST))) continue;
+            const int k = kb + u;
+            const double cc = u == 0 ? ccur : cn[u - 1];
+            const double cm = u == 0 ? cprev : (u == 1 ? ccur : cn[u - 2]);
+            if (k >= k1) continue;
+            const long long s = col + pl * k;
+            const bool t = k & 1;
+            const double cpx = t ? q.cpx[1] : q.cpx[0], cmx = t ? q.cmx[1] : q.cmx[0];
+            const int oxp = t ? q.oxp[1] : q.oxp[0], oxm = t ? q.oxm[1] : q.oxm[0];
+            const double xpv = oxp == 0 ? cc : xs[u], xmv = oxm == 0 ? cc : xs[u];
+            const double czp = L.cp[2][k], czm = L.cm[2][k];  // zero at the walls
+            const double dg = cpx + cmx + q.cpy + q.cmy + czp + czm;
+            const double nb = cpx * xpv + cmx * xmv + q.cpy * yp[u] + q.cmy * ym[u] + czp * cn[u] + czm * cm;
+            if (fl[u] & (F_SOLID | F_MGHOST)) continue;
             double b0 = bb[u];
             if (s == pin_s) b0 -= sink[0];
-            st(xc, s, (nb[u] - b0) / dg[u]);
+            st(xc, s, (nb - b0) / dg);
         }
+        cprev = cn[U0 - 2];
+        ccur = cn[U0 - 1];
     }
 }
 
