@@ -124,7 +124,9 @@ typedef struct poisson_stats {
  * non-linear and the inner Krylov iteration slows down below ~1e-3.
  * Refinement switches to an FP64 BiCGSTAB on the remaining residual when an
  * outer step makes the FP64 residual larger (that step is undone) or when an
- * inner solve stops at max_iter before its tolerance. */
+ * inner solve stops before its tolerance: at max_iter, or when it has not
+ * halved its residual within 12 iterations (FP32 vectors cannot resolve a
+ * correction below about kappa * 6e-8 of the residual). */
 void poisson_default_opts(poisson_opts *opts);
 
 /*

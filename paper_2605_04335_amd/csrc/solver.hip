@@ -502,6 +502,8 @@ void read_scalars(poisson_ctx &c, hipStream_t s)
 
 // Right-preconditioned BiCGSTAB on A y = rhs; y starts at zero.  Returns the
 // iteration count; *rc gets the status.
+constexpr int INNER_STALL = 12;
+
 template <class T, class TX>
 int bicgstab(poisson_ctx &c, const T *rhs, TX *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, double tol, int maxit,
              bool true_check, hipGraphExec_t *graph, hipStream_t s, int *rc, double *relout)
@@ -553,6 +555,11 @@ int bicgstab(poisson_ctx &c, const T *rhs, TX *y, T *r, T *rh, T *p, T *v, T *ph
     }
     int it = 0;
     double rel = 1.0;
+    // inner solves stop once they no longer halve their residual within
+    // INNER_STALL iterations: FP32 vectors cannot resolve corrections below
+    // about kappa * u32, and refinement then continues in FP64
+    double mark = 1.0;
+    int mark_it = 0;
     while (it < maxit) {
         ++it;
         if (use_graph) IBM_HIP(hipGraphLaunch(*graph, s));
@@ -578,6 +585,15 @@ int bicgstab(poisson_ctx &c, const T *rhs, TX *y, T *r, T *rh, T *p, T *v, T *ph
             k_dot2<T><<<W.nb, TPB, 0, s>>>(W, rh, r, c.part.p, PSTRIDE);
             fin(c, W.nb, FIN_REPLACE, 0, 0.0, s);
             continue;
+        }
+        if constexpr (!std::is_same<T, TX>::value) {
+            if (rel < 0.5 * mark) {
+                mark = rel;
+                mark_it = it;
+            } else if (it - mark_it >= INNER_STALL) {
+                if (log_enabled()) fprintf(stderr, "[ibm]   inner stagnation at %.3e after %d iterations\n", rel, it);
+                break;  // *rc stays IBM_ENOCONV
+            }
         }
         if (st == 1.0) {  // rho breakdown: restart with rh = r
             k_fill<T><<<W.nb, TPB, 0, s>>>(W, p, 0.0);
