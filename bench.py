@@ -87,7 +87,7 @@ def measured_traffic(workload_key):
         return None
 
 
-def serving_bench(P, rates, nreq, seed=5, slots=4, budget=64 << 30):
+def serving_bench(P, rates, nreq, seed=5, slots=8, budget=64 << 30):
     """Poisson arrivals of mixed-precision solve requests (grid edge
     log-uniform in [64, 384], cube or 2:1:1, 1-4 bodies, tol 1e-8) into the
     continuous-batching server; latency = done - submit on the server clock."""
@@ -278,7 +278,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-moving", action="store_true", help="skip the moving-body time-step measurement")
     ap.add_argument("--no-ad", action="store_true", help="skip the advection-diffusion step measurement")
-    ap.add_argument("--serve-rates", default="5,20,80", help="request arrival rates (req/s) of the serving sweep")
+    ap.add_argument("--serve-rates", default="5,20,80,200", help="request arrival rates (req/s) of the serving sweep")
     ap.add_argument("--serve-requests", type=int, default=24, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with 3 plain device copies of 1 GiB (reference for HBM byte counters)")

@@ -1,5 +1,6 @@
-"""Full-size checks on the 512^3 membrane configuration the benchmark times
-(needs an MI355X).
+"""Full-size checks on the benchmark configurations (needs an MI355X): the
+512^3 membrane case the benchmark times, the 1024^3 spheres case and the
+256^3 plain FP64 case.
 
 At this size the oracle still classifies, builds the ghost rows, applies the
 operator and runs one V-cycle in seconds, so those are compared element by
@@ -162,3 +163,35 @@ def test_c4_manufactured_fp64(c4):
     say("c4 fp64: its %d residual %.2e error %.2e" % (stats.iterations, stats.rel_residual, err))
     assert stats.status == 0 and stats.rel_residual <= 1e-11
     assert err < 1e7 * 1e-11
+
+
+# ---------------------------------------------------------------- 256^3 plain FP64 configuration
+def test_c2_full_size_matches_oracle():
+    """256^3 tanh-stretched grid, sphere + rotated ellipsoid, noise RHS (the
+    plain FP64 configuration): classification bit-exact, and with the oracle
+    solving the same system to 1e-13 the GPU FP64 solve (to 1e-12) matches it
+    to 1e-10 and the mixed solve (to 1e-10) to 1e-8, relative L2."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_04335_amd as P
+    p = W.sphere_ellipsoid_case(256)
+    say("c2 oracle set-up and solve")
+    O = oracle.setup(p.xf, p.yf, p.zf, p.bodies)
+    xo, _, _, info = oracle.solve_problem(O, p.f, tol=1e-13, maxit=100)
+    assert info.rc == 0
+    flags, _ = P.classify(p.xf, p.yf, p.zf, p.bodies)
+    assert np.array_equal(flags.cpu().numpy(), O.flags)
+    st = P.build_ghost_stencils(p.xf, p.yf, p.zf, p.bodies, flags)
+    f = torch.from_numpy(p.f).cuda()
+    s64 = P.Solver(p.xf, p.yf, p.zf, flags, st, precision="fp64", tol=1e-12, max_iter=100)
+    x64, st64 = s64.solve(f)
+    e64 = rel(x64.cpu().numpy(), xo)
+    del s64
+    smx = P.Solver(p.xf, p.yf, p.zf, flags, st, precision="mixed", tol=1e-10, max_iter=60, max_outer=20)
+    xm, stm = smx.solve(f)
+    em = rel(xm.cpu().numpy(), xo)
+    say("c2: fp64 %d its, error vs oracle %.2e; mixed %d its (%d outer), error %.2e" %
+        (st64.iterations, e64, stm.iterations, stm.outer_steps, em))
+    assert st64.status == 0 and e64 < 1e-10
+    assert stm.status == 0 and em < 1e-8
