@@ -1053,7 +1053,10 @@ static void project_mean(const Level *L, double *b)
         if (L->m[p] & 1) b[p] -= mean;
 }
 
-/* restriction: coarse RHS = volume-weighted mean of the active children's residuals */
+/* restriction (finite-volume): coarse RHS = the volume integral of the
+ * active children's residuals over the coarse cell, sum V r / V_coarse; the
+ * coarse operator is per full coarse volume, so a coarse cell cut by a body
+ * receives the residual of its fluid part only */
 static void restrict_res(const Level *F, const double *r, Level *C)
 {
 #pragma omp parallel for
@@ -1070,7 +1073,7 @@ static void restrict_res(const Level *F, const double *r, Level *C)
                     sv += V;
                     svr += V * r[p];
                 }
-                C->b[P] = sv > 0.0 ? svr / sv : 0.0;
+                C->b[P] = sv > 0.0 ? svr / (C->w[0][I] * C->w[1][J] * C->w[2][K]) : 0.0;
             }
 }
 

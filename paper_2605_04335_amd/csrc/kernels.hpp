@@ -855,8 +855,10 @@ __device__ __forceinline__ bool child_res(const Lv &F, long long pin, const T *x
     }
 }
 
-// fused residual + restriction: coarse RHS = volume-weighted mean of the
-// active children's residuals; partial sums of V_C b_C for the coarse mean
+// fused residual + restriction: coarse RHS = the volume integral of the
+// active children's residuals divided by the full coarse-cell volume (the
+// coarse operator is per full volume); partial sums of V_C b_C for the
+// coarse mean
 template <bool FINE, class T, class TB, class TBc>
 __device__ __forceinline__ double restrict_one(const Lv &F, const Lv &C, long long pin, const T *x, const TB *b,
                                                const double *bsh, const T *rsp, TBc *bc, int cc, int hc, int J,
@@ -876,8 +878,9 @@ __device__ __forceinline__ double restrict_one(const Lv &F, const Lv &C, long lo
         sv += V;
         svr += V * r;
     }
-    st(bc, sc, sv > 0.0 ? svr / sv : 0.0);
-    return (C.f[sc] & 1) ? C.w[0][I] * C.w[1][J] * C.w[2][K] * ld(bc, sc) : 0.0;
+    const double VC = C.w[0][I] * C.w[1][J] * C.w[2][K];
+    st(bc, sc, sv > 0.0 ? svr / VC : 0.0);
+    return (C.f[sc] & 1) ? VC * ld(bc, sc) : 0.0;
 }
 
 // one thread per coarse cell in natural x order (Gc tiles I over C.nx), so a
@@ -1010,7 +1013,7 @@ __global__ void __launch_bounds__(TPB) k0_restrict_res(Lv F, Lv C, Geo Gc, long 
                 svr += V * r;
             }
             const long long sc = slot(C, (I + J + K) & 1, I >> 1, J, K);
-            st(bc, sc, sv > 0 ? (double)(svr / sv) : 0.0);
+            st(bc, sc, sv > 0 ? (double)(svr / (R)(C.w[0][I] * C.w[1][J] * C.w[2][K])) : 0.0);
             if (C.f[sc] & 1) a.v[0] += C.w[0][I] * C.w[1][J] * C.w[2][K] * ld(bc, sc);
 #pragma unroll
             for (int c = 0; c < 2; ++c)
