@@ -284,7 +284,7 @@ def main():
                     help="finish with 3 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the PPE solve on a single MI355X; "
+        print("bench.py measures one GPU only: the PPE solve runs on a single MI355X; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
