@@ -27,6 +27,23 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def rel_mod_const(x, xt, flags):
+    """Relative error modulo a constant.  The pressure is defined up to a
+    constant; the pinned system fixes it only through a single cell, so its
+    near-null vector (a constant minus the pin's point-source response) is
+    not resolved by the residual and a solve that meets the tolerance may
+    carry a near-constant error of any size below kappa * tol.  The error is
+    therefore measured after removing its mean over the fluid cells from
+    every active unknown."""
+    N = len(flags)
+    fluid = (flags & 1) == 0
+    act = refpy.active_mask(flags, len(x) - N)
+    e = x - xt
+    e = np.where(act, e - e[:N][fluid].mean(), 0.0)
+    t = np.where(act, xt - xt[:N][fluid].mean(), 0.0)
+    return float(np.linalg.norm(e) / np.linalg.norm(t))
+
+
 @pytest.fixture(scope="module")
 def c3():
     import torch
@@ -94,8 +111,8 @@ def test_c3_manufactured_mixed_and_fp64(c3):
     x64, st64 = s64.solve_assembled(bd)
     x64 = x64.cpu().numpy()
     r64 = np.linalg.norm(b - oracle.apply(p.xf, p.yf, p.zf, O.flags, O.st, x64)) / nb
-    say("fp64: its %d, own residual %.2e, oracle residual %.2e, error %.2e" %
-        (st64.iterations, st64.rel_residual, r64, rel(x64, xt)))
+    say("fp64: its %d, own residual %.2e, oracle residual %.2e, error %.2e (modulo a constant %.2e)" %
+        (st64.iterations, st64.rel_residual, r64, rel(x64, xt), rel_mod_const(x64, xt, O.flags)))
     assert st64.status == 0 and r64 <= 1.01e-12
     del s64
     torch.cuda.empty_cache()
@@ -107,14 +124,14 @@ def test_c3_manufactured_mixed_and_fp64(c3):
     say("mixed: its %d outer %d, own residual %.2e, oracle residual %.2e, error %.2e, vs fp64 %.2e" %
         (stm.iterations, stm.outer_steps, stm.rel_residual, rm, rel(xm, xt), rel(xm, x64)))
     assert stm.status == 0 and rm <= 1.01e-12
-    # kappa ~ (12 / h_min^2) / (3 pi^2) ~ 3e5 on this grid bounds each error
-    # by kappa * residual (a 1e-8 solution match is not implied by any
-    # attainable residual here); iterative refinement must reach the FP64
-    # residual, so the mixed solution is held to the same bound
+    # kappa ~ (12 / h_min^2) / (3 pi^2) ~ 3e5 of the Laplacian bounds each
+    # error modulo a constant by kappa * residual (a 1e-8 solution match is
+    # not implied by any attainable residual here); iterative refinement must
+    # reach the FP64 residual, so the mixed solution is held to the same bound
     kappa = 3e5
-    assert rel(x64, xt) < kappa * 1e-12, rel(x64, xt)
-    assert rel(xm, xt) < kappa * 1e-12, rel(xm, xt)
-    assert rel(xm, x64) < kappa * 2e-12, rel(xm, x64)
+    assert rel_mod_const(x64, xt, O.flags) < kappa * 1e-12
+    assert rel_mod_const(xm, xt, O.flags) < kappa * 1e-12
+    assert rel_mod_const(xm, x64, O.flags) < kappa * 2e-12
 
 
 # ---------------------------------------------------------------- 1024^3, 20 spheres
@@ -140,10 +157,10 @@ def test_c4_classification(c4):
 
 
 def test_c4_manufactured_fp64(c4):
-    """b = A x_true on 1024^3: the FP64 solve meets 1e-11 and its error stays
-    within kappa * tol.  The pinned system's smallest singular value is set by
-    its single pin row, so kappa is well above the Laplacian's (12/h^2)/(3 pi^2)
-    ~ 4e5: the measured error/residual ratio at 1e-10 is 2.8e6."""
+    """b = A x_true on 1024^3: the FP64 solve meets 1e-11 and its error
+    modulo a constant stays within kappa * tol with the Laplacian's
+    kappa = (12/h^2)/(3 pi^2) ~ 4e5 (the near-constant part of the error
+    reached 1.7e-4 in one run: the single-cell pin does not resolve it)."""
     import torch
     P, p = c4
     flags, cst = P.classify(p.xf, p.yf, p.zf, p.bodies)
@@ -159,10 +176,12 @@ def test_c4_manufactured_fp64(c4):
     del xd
     say("c4 fp64 solve")
     x, stats = sol.solve_assembled(b)
-    err = float(torch.linalg.norm(x.cpu() - torch.from_numpy(xt)) / np.linalg.norm(xt))
-    say("c4 fp64: its %d residual %.2e error %.2e" % (stats.iterations, stats.rel_residual, err))
+    xn = x.cpu().numpy()
+    err = rel_mod_const(xn, xt, fl)
+    say("c4 fp64: its %d residual %.2e error %.2e, modulo a constant %.2e" % (stats.iterations, stats.rel_residual,
+                                                                            rel(xn, xt), err))
     assert stats.status == 0 and stats.rel_residual <= 1e-11
-    assert err < 1e7 * 1e-11
+    assert err < 4e5 * 1e-11
 
 
 # ---------------------------------------------------------------- 256^3 plain FP64 configuration
