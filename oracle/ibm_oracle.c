@@ -1077,7 +1077,9 @@ static void restrict_res(const Level *F, const double *r, Level *C)
             }
 }
 
-/* prolongation: trilinear in physical coordinates, added to active cells */
+/* prolongation: trilinear in physical coordinates over the active coarse
+ * nodes (weights renormalised: a node inside a body carries no correction),
+ * added to active cells */
 static void prolong_add(const Level *F, const Level *C, const double *xc, double *xf)
 {
 #pragma omp parallel for
@@ -1088,13 +1090,16 @@ static void prolong_add(const Level *F, const Level *C, const double *xc, double
                 if (!(F->m[p] & 1)) continue;
                 int I = F->pi[0][i], J = F->pi[1][j], K = F->pi[2][k];
                 double tx = F->pt[0][i], ty = F->pt[1][j], tz = F->pt[2][k];
-                double v = 0.0;
+                double v = 0.0, sw = 0.0;
                 for (int c = 0; c < 8; ++c) {
                     int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+                    int64_t q = IDX(C->n, I + dx, J + dy, K + dz);
+                    if (!(C->m[q] & 1)) continue;
                     double wgt = (dx ? tx : 1.0 - tx) * (dy ? ty : 1.0 - ty) * (dz ? tz : 1.0 - tz);
-                    v += wgt * xc[IDX(C->n, I + dx, J + dy, K + dz)];
+                    v += wgt * xc[q];
+                    sw += wgt;
                 }
-                xf[p] += v;
+                if (sw > 0.0) xf[p] += v / sw;
             }
 }
 

@@ -1039,12 +1039,33 @@ __device__ __forceinline__ double coarse_val(const Lv &C, const Tc *xc, int I, i
     return ld(xc, slot(C, (I + J + K) & 1, I >> 1, J, K));
 }
 
-// trilinear interpolation (physical coordinates) of the coarse correction at one fine cell
+template <class Tc>
+__device__ __forceinline__ double coarse_act(const Lv &C, int I, int J, int K)
+{
+    return (C.f[slot(C, (I + J + K) & 1, I >> 1, J, K)] & 1) ? 1.0 : 0.0;
+}
+
+// trilinear interpolation (physical coordinates) of the coarse correction at
+// one fine cell over the active coarse nodes, weights renormalised (an
+// inactive node, inside a body, carries no correction)
 template <class Tc>
 __device__ __forceinline__ double interp(const Lv &C, const PMap &M, const Tc *xc, int i, int j, int k)
 {
     const int I = M.pi[0][i], J = M.pi[1][j], K = M.pi[2][k];
     const double tx = M.pt[0][i], ty = M.pt[1][j], tz = M.pt[2][k];
+    double num = 0.0, den = 0.0;
+    int na = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+        const double w = (dz ? tz : 1 - tz) * (dy ? ty : 1 - ty) * (dx ? tx : 1 - tx);
+        const double a = coarse_act<Tc>(C, I + dx, J + dy, K + dz);
+        num += w * a * coarse_val(C, xc, I + dx, J + dy, K + dz);
+        den += w * a;
+        na += a > 0.0;
+    }
+    if (na < 8) return den > 0.0 ? num / den : 0.0;
+    // all nodes active: the plain trilinear form (its weights sum to one)
     return (1 - tz) * ((1 - ty) * ((1 - tx) * coarse_val(C, xc, I, J, K) + tx * coarse_val(C, xc, I + 1, J, K)) +
                        ty * ((1 - tx) * coarse_val(C, xc, I, J + 1, K) + tx * coarse_val(C, xc, I + 1, J + 1, K))) +
            tz * ((1 - ty) * ((1 - tx) * coarse_val(C, xc, I, J, K + 1) + tx * coarse_val(C, xc, I + 1, J, K + 1)) +
@@ -1066,12 +1087,16 @@ __device__ __forceinline__ void prolong_one(const Lv &F, const Lv &C, const PMap
 // Prolongation by coarse column: one thread per coarse (I, J) column walks
 // its K range with the 3x3 coarse neighbourhoods of planes K-1, K, K+1 in
 // registers (one new plane per step) and corrects the 8 children of each
-// coarse cell: trilinear in physical coordinates, clamped at the walls, in
-// the precision of the fine iterate.
+// coarse cell: trilinear in physical coordinates over the active coarse
+// nodes (weights renormalised), clamped at the walls, in the precision of
+// the fine iterate.
 // SKIP_RED: the red half-sweep that follows overwrites every regular red
 // cell without reading it, so only black slots (and, on level 0, the red
 // ghost and membrane cells, which later rows read) receive the correction.
-template <bool FINE, class Tc, class Tf, bool SKIP_RED>
+// RENORM: the coarse level has inactive cells, so weights are renormalised
+// over the active nodes (without inactive cells the plain trilinear weights
+// are the same and the activity loads are skipped).
+template <bool FINE, class Tc, class Tf, bool SKIP_RED, bool RENORM>
 __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, const Tc *__restrict__ xc,
                                                    Tf *__restrict__ xf)
 {
@@ -1080,8 +1105,10 @@ __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, c
     if (!geo_tile(Gc, I, J, k0, k1)) return;
     const int Ie[3] = {max(I - 1, 0), I, min(I + 1, C.nx - 1)};
     const int Jb[3] = {max(J - 1, 0), J, min(J + 1, C.ny - 1)};
-    R va[3][3], vb[3][3], vn[3][3];
-    auto plane = [&](int kk, R (&v)[3][3]) {
+    // coarse values (zero where inactive) and activity (0/1) of the 3x3
+    // neighbourhoods of planes K-1, K, K+1
+    R va[3][3], vb[3][3], vn[3][3], aa[3][3], ab[3][3], an[3][3];
+    auto plane = [&](int kk, R (&v)[3][3], R (&a)[3][3]) {
         const long long zo = (long long)C.H * C.ny * kk;
 #pragma unroll
         for (int b = 0; b < 3; ++b)
@@ -1089,7 +1116,12 @@ __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, c
             for (int e = 0; e < 3; ++e) {
                 const long long sc = (((Ie[e] + Jb[b] + kk) & 1) ? C.Nh : 0) + (Ie[e] >> 1) +
                                      (long long)C.H * Jb[b] + zo;
-                v[b][e] = (R)ld(xc, sc);
+                if constexpr (RENORM) {
+                    a[b][e] = (C.f[sc] & 1) ? (R)1 : (R)0;
+                    v[b][e] = a[b][e] * (R)ld(xc, sc);
+                } else {
+                    v[b][e] = (R)ld(xc, sc);
+                }
             }
     };
     // per child direction: does the 2-point box start at the cell (offset 1)
@@ -1104,10 +1136,10 @@ __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, c
         ty[d] = (R)M.pt[1][2 * J + d];
     }
     const long long fpl = (long long)F.H * F.ny;
-    plane(max(k0 - 1, 0), va);
-    plane(k0, vb);
+    plane(max(k0 - 1, 0), va, aa);
+    plane(k0, vb, ab);
     for (int K = k0; K < k1; ++K) {
-        plane(min(K + 1, C.nz - 1), vn);
+        plane(min(K + 1, C.nz - 1), vn, an);
         // flags of the 8 children and the values to be corrected, issued
         // together (red values only when they are corrected at all)
         uint8_t fq[8];
@@ -1125,20 +1157,27 @@ __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, c
             const int k = 2 * K + dz;
             const bool ez = M.pi[2][k] != K - 1;
             const R tz = (R)M.pt[2][k];
-            // z, then y, then x
-            R zz[3][3];
+            // z, then y, then x, for the values and for the weights
+            R zz[3][3], zw[3][3];
 #pragma unroll
             for (int b = 0; b < 3; ++b)
 #pragma unroll
-                for (int e = 0; e < 3; ++e)
+                for (int e = 0; e < 3; ++e) {
                     zz[b][e] = ez ? (1 - tz) * vb[b][e] + tz * vn[b][e] : (1 - tz) * va[b][e] + tz * vb[b][e];
+                    if constexpr (RENORM)
+                        zw[b][e] = ez ? (1 - tz) * ab[b][e] + tz * an[b][e] : (1 - tz) * aa[b][e] + tz * ab[b][e];
+                }
 #pragma unroll
             for (int dy = 0; dy < 2; ++dy) {
-                R yy[3];
+                R yy[3], yw[3];
 #pragma unroll
-                for (int e = 0; e < 3; ++e)
+                for (int e = 0; e < 3; ++e) {
                     yy[e] = ey[dy] ? (1 - ty[dy]) * zz[1][e] + ty[dy] * zz[2][e]
                                    : (1 - ty[dy]) * zz[0][e] + ty[dy] * zz[1][e];
+                    if constexpr (RENORM)
+                        yw[e] = ey[dy] ? (1 - ty[dy]) * zw[1][e] + ty[dy] * zw[2][e]
+                                       : (1 - ty[dy]) * zw[0][e] + ty[dy] * zw[1][e];
+                }
 #pragma unroll
                 for (int dx = 0; dx < 2; ++dx) {
                     const int q = dx + 2 * dy + 4 * dz;
@@ -1153,8 +1192,14 @@ __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, c
                     } else {
                         xv = xq[q];
                     }
-                    const R val = ex[dx] ? (1 - tx[dx]) * yy[1] + tx[dx] * yy[2] : (1 - tx[dx]) * yy[0] + tx[dx] * yy[1];
-                    xf[s] = (Tf)((R)xv + val);
+                    const R num = ex[dx] ? (1 - tx[dx]) * yy[1] + tx[dx] * yy[2] : (1 - tx[dx]) * yy[0] + tx[dx] * yy[1];
+                    if constexpr (RENORM) {
+                        const R den = ex[dx] ? (1 - tx[dx]) * yw[1] + tx[dx] * yw[2]
+                                             : (1 - tx[dx]) * yw[0] + tx[dx] * yw[1];
+                        xf[s] = (Tf)((R)xv + (den > (R)0 ? num / den : (R)0));
+                    } else {
+                        xf[s] = (Tf)((R)xv + num);
+                    }
                 }
             }
         }
@@ -1164,6 +1209,10 @@ __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, c
             for (int e = 0; e < 3; ++e) {
                 va[b][e] = vb[b][e];
                 vb[b][e] = vn[b][e];
+                if constexpr (RENORM) {
+                    aa[b][e] = ab[b][e];
+                    ab[b][e] = an[b][e];
+                }
             }
     }
 }

@@ -130,14 +130,16 @@ __global__ void __launch_bounds__(TPB) k_coarse_active(int fnx, int fny, int cnx
     }
 }
 
-// coarse mask in split layout (CM_* bits: active, open +faces, open -faces)
-// and the volume of the active cells.  A face is open when both cells are
-// active and no child link across it is cut.
+// coarse mask in split layout (CM_* bits: active, open +faces, open -faces),
+// the volume of the active cells and the count of inactive cells (partials
+// at part and part + pstride).  A face is open when both cells are active and
+// no child link across it is cut.
 __global__ void __launch_bounds__(TPB) k_coarse_mask(Lv L, Walk W, const uint8_t *__restrict__ ha,
-                                                     uint8_t *__restrict__ sm, double *part)
+                                                     uint8_t *__restrict__ sm, double *part, int pstride)
 {
-    Acc<1> s;
+    Acc<2> s;
     s.v[0] = 0.0;
+    s.v[1] = 0.0;
     WALK_BEGIN(W, p)
         int c, h, j, k, i;
         decode_slot(L, p, c, h, j, k, i);
@@ -145,6 +147,7 @@ __global__ void __launch_bounds__(TPB) k_coarse_mask(Lv L, Walk W, const uint8_t
         if (i < L.nx) {
             const long long P = (long long)i + (long long)L.nx * (j + (long long)L.ny * k);
             const uint8_t a = ha[P];
+            if (!(a & 1)) s.v[1] += 1.0;
             if (a & 1) {
                 out = CM_ACT;
                 s.v[0] += L.w[0][i] * L.w[1][j] * L.w[2][k];
@@ -162,7 +165,7 @@ __global__ void __launch_bounds__(TPB) k_coarse_mask(Lv L, Walk W, const uint8_t
         }
         sm[p] = out;
     WALK_END
-    block_reduce<1>(s, part, 0, blockIdx.x);
+    block_reduce<2>(s, part, pstride, blockIdx.x);
 }
 
 }  // namespace

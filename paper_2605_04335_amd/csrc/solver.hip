@@ -43,6 +43,7 @@ struct Level {
     DBuf<int> pi[3];                 // prolongation map from the coarse parent
     DBuf<double> pt[3];
     double volA = 0.0;               // volume of the active cells
+    long long n_inactive = 0;        // coarse levels: inactive cells (inside bodies)
     Geo geo;                         // tiles over (h, j, k) of one colour
     Geo geon;                        // tiles over (i, j, k): restriction into this level
     Walk walk;                       // over 2 Nh slots
@@ -290,6 +291,22 @@ struct Store<float> {
     static TB *b(Level &L) { return L.b16.p; }
 };
 
+// prolongation of coarse level C onto F; the renormalised form only where C
+// has inactive cells
+template <bool FINE, class Tc, class Tf>
+void launch_prolong(const Level &F, const Level &C, bool skip_red, const Tc *xc, Tf *xf, hipStream_t s)
+{
+    const bool rn = C.n_inactive > 0;
+    if (skip_red && rn)
+        k_prolong_z<FINE, Tc, Tf, true, true><<<C.geon.nb, TPB, 0, s>>>(F.lv, C.lv, F.pm, C.geon, xc, xf);
+    else if (skip_red)
+        k_prolong_z<FINE, Tc, Tf, true, false><<<C.geon.nb, TPB, 0, s>>>(F.lv, C.lv, F.pm, C.geon, xc, xf);
+    else if (rn)
+        k_prolong_z<FINE, Tc, Tf, false, true><<<C.geon.nb, TPB, 0, s>>>(F.lv, C.lv, F.pm, C.geon, xc, xf);
+    else
+        k_prolong_z<FINE, Tc, Tf, false, false><<<C.geon.nb, TPB, 0, s>>>(F.lv, C.lv, F.pm, C.geon, xc, xf);
+}
+
 // level-0 smoothing step: for red then black, the dense half-sweep, the
 // membrane-adjacent cells of that colour, then Jacobi on all ghost unknowns
 template <class T>
@@ -403,19 +420,11 @@ void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
         for (int l = std::min(lt, nl - 1) - 1; l >= 1; --l) {
             Level &L = c.lv[l];
             Level &C = c.lv[l + 1];
-            if (o.nu2 > 0)
-                k_prolong_z<false, Tc, Tc, true><<<C.geon.nb, TPB, 0, s>>>(L.lv, C.lv, L.pm, C.geon, Store<T>::x(C),
-                                                                           Store<T>::x(L));
-            else
-                k_prolong_z<false, Tc, Tc, false><<<C.geon.nb, TPB, 0, s>>>(L.lv, C.lv, L.pm, C.geon, Store<T>::x(C),
-                                                                            Store<T>::x(L));
+            launch_prolong<false>(L, C, o.nu2 > 0, Store<T>::x(C), Store<T>::x(L), s);
             coarse_smooth<Tc, TB>(L, o.nu2, false, c.sc.p + S_MEAN0 + l, s);
         }
         Level &L0v = c.lv[0];
-        if (o.nu2 > 0)
-            k_prolong_z<true, Tc, T, true><<<L1.geon.nb, TPB, 0, s>>>(L0v.lv, L1.lv, L0v.pm, L1.geon, Store<T>::x(L1), x);
-        else
-            k_prolong_z<true, Tc, T, false><<<L1.geon.nb, TPB, 0, s>>>(L0v.lv, L1.lv, L0v.pm, L1.geon, Store<T>::x(L1), x);
+        launch_prolong<true>(L0v, L1, o.nu2 > 0, Store<T>::x(L1), x, s);
         IBM_LAUNCH_CHECK();
     }
     for (int it = 0; it < o.nu2; ++it) fine_smooth<T>(c, x, b, sink, false, s);
@@ -747,18 +756,22 @@ void setup_geometry(poisson_ctx &c, const uint8_t *flags, const ibm_stencils *st
         const uint8_t *fine = l == 1 ? flags : c.hact[l & 1].p;
         uint8_t *ha = c.hact[(l + 1) & 1].p;
         k_coarse_active<<<blocks(C.N), TPB, 0, s>>>(F.n[0], F.n[1], C.n[0], C.n[1], C.N, fine, l == 1, ha);
-        k_coarse_mask<<<C.walk.nb, TPB, 0, s>>>(C.lv, C.walk, ha, C.m.p, c.part.p);
+        k_coarse_mask<<<C.walk.nb, TPB, 0, s>>>(C.lv, C.walk, ha, C.m.p, c.part.p, PSTRIDE);
         k_fin<<<1, 1024, 0, s>>>(c.part.p, PSTRIDE, C.walk.nb, FIN_SUM, l, 0.0, c.ssum.p);
+        k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, C.walk.nb, FIN_SUM, 16 + l, 0.0, c.ssum.p);
     }
     IBM_LAUNCH_CHECK();
     double hs[32];
     int herr = 0;
-    IBM_HIP(hipMemcpyAsync(hs, c.ssum.p, nl * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipMemcpyAsync(hs, c.ssum.p, 32 * sizeof(double), hipMemcpyDeviceToHost, s));
     IBM_HIP(hipMemcpyAsync(&herr, c.serr.p, sizeof(int), hipMemcpyDeviceToHost, s));
     IBM_HIP(hipStreamSynchronize(s));
     IBM_REQUIRE(herr == 0, IBM_EGEOM, "cut link without ghost");
     c.vol_fluid = hs[0];
-    for (int l = 1; l < nl; ++l) c.lv[l].volA = hs[l];
+    for (int l = 1; l < nl; ++l) {
+        c.lv[l].volA = hs[l];
+        c.lv[l].n_inactive = (long long)hs[16 + l];
+    }
     Sp &S = c.sp;
     S.N2 = c.N2;
     S.pin = c.pin;
