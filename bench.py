@@ -67,6 +67,36 @@ def sweep_source_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
+def solver_source_digest():
+    """Digest of every kernel and host source of the solve: whole-solve HBM
+    counters describe only the version they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "setup.hpp", "solver.hip", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2605_04335_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_solve_traffic(workload_key):
+    """HBM bytes of one whole mixed solve (FETCH_SIZE + WRITE_SIZE of every
+    solve kernel, scaled by a plain copy) from the committed rocprofv3
+    summary, or None when missing or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "mg_bicgstab_%s_solve_traffic.md" % workload_key)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_digest") != solver_source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_solve"])
+    except (KeyError, ValueError):
+        return None
+
+
 def measured_traffic(workload_key):
     """HBM bytes per launch of k0_sweep from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
@@ -360,6 +390,13 @@ def main():
                       "setup_s": round(setup_s, 2), "ghosts": ng, "membrane_ghosts": nm, "fallback_rows": nfb},
            "roofline": roof,
            "kernel_ms": {k: {"total_ms": round(v[0], 3), "launches": v[1]} for k, v in kern_ms.items()}}
+    # whole solve: measured HBM bytes of every solve kernel over the solve time
+    ts = measured_solve_traffic({"c3": "membrane512", "c2": "spheroids256", "c4": "spheres1024",
+                                 "c1": "sphere32"}[args.config])
+    if ts:
+        gbs = ts / (ms_per_step * 1e-3) / 1e9
+        out["solve_hbm"] = {"bytes_per_solve": int(ts), "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
     if not args.no_fp64:
         del solm
