@@ -752,37 +752,103 @@ __global__ void __launch_bounds__(TPB) k0_jacobi_sparse(Lv L, Sp S, const T *xo,
     }
 }
 
+// stencil of ghost row r (8 columns, 8 weights) by 16-byte loads
+__device__ __forceinline__ void ghost_stencil(const Sp &S, int r, int32_t (&gc)[8], double (&gw)[8])
+{
+    const int4 *c4 = reinterpret_cast<const int4 *>(S.rcol + 8 * (long long)r);
+    const double2 *w2 = reinterpret_cast<const double2 *>(S.rw + 8 * (long long)r);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int4 q = c4[t];
+        gc[4 * t] = q.x; gc[4 * t + 1] = q.y; gc[4 * t + 2] = q.z; gc[4 * t + 3] = q.w;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double2 q = w2[t];
+        gw[2 * t] = q.x; gw[2 * t + 1] = q.y;
+    }
+}
+
+// sum w x over a preloaded ghost stencil, in column order (as ghost_sum)
+template <class T>
+__device__ __forceinline__ double stencil_sum(const T *x, long long fallback, const int32_t (&gc)[8], const double (&gw)[8])
+{
+    double xv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) xv[t] = ld(x, gc[t] >= 0 ? (long long)gc[t] : fallback);
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        if (gc[t] >= 0) acc += gw[t] * xv[t];
+    return acc;
+}
+
 // membrane-adjacent cells of one colour (after the dense half-sweep): across
 // a cut link the neighbour's ghost unknown is eliminated, i.e. replaced by
 // the current value of its stencil, sum w x - b/sG
 // All cells of the colour read the same iterate (their eliminated stencils
 // may reach each other): new values go to tmp, k0_mscat writes them.
+// The loads go out in batches (the row's indices; the direct neighbours and
+// the stencils of its first two cut links; the stencil values), so a row
+// waits on three dependent steps rather than on one per neighbour; a third
+// or later cut link takes the plain path.  The arithmetic and its order are
+// those of ghost_sum.
 template <class T>
 __global__ void __launch_bounds__(TPB) k0_msweep(Lv L, Sp S, const T *x, const T *b, int color, double *tmp)
 {
     for (int m = blockIdx.x * TPB + threadIdx.x; m < S.nm; m += gridDim.x * TPB) {
-        if (S.mcolor[m] != color) continue;
+        const int mcl = S.mcolor[m];
         const long long u = S.mslot[m];
+        int32_t mc[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) mc[q] = S.mcol[6 * m + q];
+        if (mcl != color) continue;
         int c, h, j, k, i;
         decode_slot(L, u, c, h, j, k, i);
-        const int32_t *mc = S.mcol + 6 * m;
         const double cf[6] = {L.cm[0][i], L.cp[0][i], L.cm[1][j], L.cp[1][j], L.cm[2][k], L.cp[2][k]};
+        const double bu = ld(b, u);
+        // direct neighbours (a wall or cut link reads the row's own slot, unused)
+        // and the ghost rows of the first two cut links
+        double v[6];
+        int ra = -1, rb = -1;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int32_t col = mc[q];
+            v[q] = ld(x, col >= 0 && col < S.N2 ? (long long)col : u);
+            if (col >= S.N2) {
+                const int r = S.ng + (int)(col - S.N2);
+                if (ra < 0) ra = r;
+                else if (rb < 0) rb = r;
+            }
+        }
+        int32_t ca[8], cb[8];
+        double wa[8], wb[8], ba = 0.0, bb = 0.0, sa = 1.0, sb = 1.0;
+        if (ra >= 0) {
+            ghost_stencil(S, ra, ca, wa);
+            ba = ld(b, S.N2 + (ra - S.ng));
+            sa = S.rsG[ra];
+        }
+        if (rb >= 0) {
+            ghost_stencil(S, rb, cb, wb);
+            bb = ld(b, S.N2 + (rb - S.ng));
+            sb = S.rsG[rb];
+        }
+        const double va = ra >= 0 ? stencil_sum(x, u, ca, wa) - ba / sa : 0.0;
+        const double vb = rb >= 0 ? stencil_sum(x, u, cb, wb) - bb / sb : 0.0;
         double off = 0.0, s = 0.0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const int32_t col = mc[q];
             if (col < 0) continue;
-            double v;
+            double val = v[q];
             if (col >= S.N2) {
                 const int r = S.ng + (int)(col - S.N2);
-                v = ghost_sum(S, x, r) - ld(b, col) / S.rsG[r];
-            } else {
-                v = ld(x, col);
+                val = r == ra ? va : r == rb ? vb : ghost_sum(S, x, r) - ld(b, col) / S.rsG[r];
             }
-            off += cf[q] * v;
+            off += cf[q] * val;
             s += cf[q];
         }
-        tmp[m] = (off - ld(b, u)) / s;
+        tmp[m] = (off - bu) / s;
     }
 }
 
