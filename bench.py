@@ -120,21 +120,31 @@ def measured_traffic(workload_key):
 def serving_bench(P, rates, nreq, seed=5, slots=8, budget=64 << 30):
     """Poisson arrivals of mixed-precision solve requests (grid edge
     log-uniform in [64, 384], cube or 2:1:1, 1-4 bodies, tol 1e-8) into the
-    continuous-batching server; latency = done - submit on the server clock."""
+    continuous-batching server; latency = done - submit on the server clock.
+    Every rate gets requests of its own (no set-up is reused from the cache),
+    and the latency is split into queueing (submit to admission), set-up
+    (classification, ghost rows, hierarchy), solve (RHS upload to solution on
+    the host) and the rest (release of the request's memory)."""
     from paper_2605_04335_amd import workloads as W
-    rng = np.random.default_rng(seed)
-    reqs = []
-    for q in range(nreq):
-        p = W.serving_request(rng)
-        p.f = W.noise_rhs(p.npts, seed + 1000 + q)
-        reqs.append(p)
+
+    def make(q0, n):
+        rng = np.random.default_rng(seed + q0)
+        reqs = []
+        for q in range(n):
+            p = W.serving_request(rng)
+            p.f = W.noise_rhs(p.npts, seed + 1000 + q0 + q)
+            reqs.append(p)
+        return reqs
+
     # one warm-up request outside the measurement (first-use costs of the runtime)
     srv = P.Server(hbm_budget=budget, max_slots=slots)
-    t = srv.submit(reqs[0].xf, reqs[0].yf, reqs[0].zf, reqs[0].bodies, reqs[0].f, precision="mixed", tol=1e-8)
+    w = make(10 ** 6, 1)[0]
+    t = srv.submit(w.xf, w.yf, w.zf, w.bodies, w.f, precision="mixed", tol=1e-8)
     while srv.poll(t, want_x=False)[0] == P.IBM_EAGAIN:
         time.sleep(0.001)
     out = []
-    for rate in rates:
+    for ri, rate in enumerate(rates):
+        reqs = make(10000 * (ri + 1), nreq)
         arr = np.cumsum(np.random.default_rng(seed + int(rate)).exponential(1.0 / rate, nreq))
         pending, done = {}, []
         t0 = time.perf_counter()
@@ -149,20 +159,30 @@ def serving_bench(P, rates, nreq, seed=5, slots=8, budget=64 << 30):
                 rc, state, _, st, tm = srv.poll(tk, want_x=False)
                 if rc == P.IBM_EAGAIN:
                     continue
-                done.append((tm.submit_ms, tm.done_ms, pending.pop(tk), rc, st.rel_residual))
+                done.append((tm.submit_ms, tm.done_ms, pending.pop(tk), rc, st.rel_residual, tm.admit_ms,
+                             tm.setup_ms, tm.solve_ms, tm.cache_hit))
             time.sleep(0.0005)
+        del reqs
         lat = np.array([d[1] - d[0] for d in done])
         span_s = (max(d[1] for d in done) - min(d[0] for d in done)) / 1e3
         pts = sum(d[2] for d in done)
         ok = sum(1 for d in done if d[3] == 0 and d[4] <= 1e-8)
+        queue = np.array([d[5] - d[0] for d in done])
+        setup = np.array([d[6] for d in done])
+        solve = np.array([d[7] for d in done])
+        rest = lat - queue - setup - solve
         out.append({"rate_req_s": rate, "requests": nreq, "ok": ok, "p50_ms": round(float(np.percentile(lat, 50)), 2),
                     "p99_ms": round(float(np.percentile(lat, 99)), 2), "solves_s": round(nreq / span_s, 2),
-                    "Mpts_s": round(pts / span_s / 1e6, 1)})
-        log("serve rate %g req/s: p50 %.1f ms p99 %.1f ms, %.1f solves/s, %.0f Mpts/s, %d/%d ok" %
-            (rate, out[-1]["p50_ms"], out[-1]["p99_ms"], out[-1]["solves_s"], out[-1]["Mpts_s"], ok, nreq))
+                    "Mpts_s": round(pts / span_s / 1e6, 1), "cache_hits": int(sum(d[8] for d in done)),
+                    "mean_ms": {"queue": round(float(queue.mean()), 2), "setup": round(float(setup.mean()), 2),
+                                "solve": round(float(solve.mean()), 2), "release": round(float(rest.mean()), 2)}})
+        log("serve rate %g req/s: p50 %.1f ms p99 %.1f ms, %.1f solves/s, %.0f Mpts/s, %d/%d ok; mean queue %.1f "
+            "set-up %.1f solve %.1f release %.1f ms" %
+            (rate, out[-1]["p50_ms"], out[-1]["p99_ms"], out[-1]["solves_s"], out[-1]["Mpts_s"], ok, nreq,
+             queue.mean(), setup.mean(), solve.mean(), rest.mean()))
     srv.close()
     return {"workload": "Poisson arrivals, edge log-uniform [64, 384], cube or 2:1:1, 1-4 bodies (spheres, "
-                        "ellipsoids, plates), noise RHS, mixed MG-BiCGSTAB to 1e-8",
+                        "ellipsoids, plates), noise RHS, mixed MG-BiCGSTAB to 1e-8; distinct requests per rate",
             "max_slots": slots, "hbm_budget_GB": budget >> 30, "sweep": out}
 
 
@@ -309,7 +329,7 @@ def main():
     ap.add_argument("--no-moving", action="store_true", help="skip the moving-body time-step measurement")
     ap.add_argument("--no-ad", action="store_true", help="skip the advection-diffusion step measurement")
     ap.add_argument("--serve-rates", default="5,20,80,200", help="request arrival rates (req/s) of the serving sweep")
-    ap.add_argument("--serve-requests", type=int, default=24, help="requests per arrival rate")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with 3 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()

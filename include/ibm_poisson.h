@@ -418,6 +418,10 @@ typedef struct poisson_req_times {
     int64_t n_unknowns;                  /* length of the solution once finished (N + n_mghost), else 0 */
     int32_t cache_hit;                   /* 1: the request reused a cached set-up (no classification,
                                             ghost rows or hierarchy build) */
+    double setup_ms;                     /* worker wall time in classification, ghost rows and
+                                            poisson_setup (0 on a cache hit) */
+    double solve_ms;                     /* worker wall time from the RHS upload to the solution on the
+                                            host (poisson_solve and the copies around it) */
 } poisson_req_times;
 
 int32_t poisson_server_create(const poisson_server_opts *opts, poisson_server **out);

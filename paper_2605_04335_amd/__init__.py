@@ -91,7 +91,8 @@ class _Request(ctypes.Structure):
 
 class ReqTimes(ctypes.Structure):
     _fields_ = [("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
-                ("n_unknowns", ctypes.c_int64), ("cache_hit", ctypes.c_int32)]
+                ("n_unknowns", ctypes.c_int64), ("cache_hit", ctypes.c_int32), ("setup_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double)]
 
 
 EXPORTS = ["ibm_classify", "ibm_build_ghost_stencils", "ibm_stencils_info", "ibm_stencils_export",

@@ -22,6 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 UNITS = {
     "capi.hip": [],
+    "memory.hip": [],
     "classify.hip": ["-ffp-contract=off"],
     "stencils.hip": ["-ffp-contract=off"],
     "solver.hip": [],

@@ -68,20 +68,32 @@ inline std::shared_mutex &capture_mutex()
     return m;
 }
 
-// Owning device buffer (hipMalloc / hipFree).
+// Device blocks from the library's cache (memory.hip): cls is the block's
+// size class, 0 for a block that bypassed the cache.  Both may throw Error.
+void *device_alloc(size_t bytes, int &dev, size_t &cls);
+void device_release(void *p, int dev, size_t cls);
+
+// Owning device buffer (device_alloc / device_release).
 template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
     bool own = true;  // false: a view into caller-owned memory (never freed here)
+    int dev = 0;      // device and size class of an owned block
+    size_t cls = 0;
     DBuf() = default;
     explicit DBuf(size_t count) { alloc(count); }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), own(o.own) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), own(o.own), dev(o.dev), cls(o.cls) { o.p = nullptr; o.n = 0; }
     DBuf &operator=(DBuf &&o) noexcept
     {
-        if (this != &o) { release(); p = o.p; n = o.n; own = o.own; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; own = o.own; dev = o.dev; cls = o.cls;
+            o.p = nullptr;
+            o.n = 0;
+        }
         return *this;
     }
     void view(T *q, size_t count)
@@ -96,28 +108,14 @@ struct DBuf {
     {
         release();
         own = true;
-        n = count;
         if (count) {
-            hipError_t e;
-            {
-                std::shared_lock<std::shared_mutex> lk(capture_mutex());
-                e = hipMalloc((void **)&p, count * sizeof(T));
-            }
-            if (e != hipSuccess) {
-                p = nullptr;
-                n = 0;
-                (void)hipGetLastError();
-                throw Error(IBM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
-                                            hipGetErrorString(e));
-            }
+            p = (T *)device_alloc(count * sizeof(T), dev, cls);
+            n = count;
         }
     }
     void release()
     {
-        if (p && own) {
-            std::shared_lock<std::shared_mutex> lk(capture_mutex());
-            (void)hipFree(p);
-        }
+        if (p && own) device_release(p, dev, cls);
         p = nullptr;
         n = 0;
         own = true;

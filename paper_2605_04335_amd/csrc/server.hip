@@ -106,10 +106,12 @@ struct poisson_server {
             if (!e.busy) b += e.bytes;
         return b;
     }
-    // free least recently used idle set-ups until `need` more bytes fit, or
-    // until at most `keep` entries remain (caller holds mu)
-    void evict(size_t need, size_t keep)
+    // drop least recently used idle set-ups until `need` more bytes fit, or
+    // until at most `keep` entries remain (caller holds mu); the caller
+    // destroys the returned set-ups after releasing mu
+    std::vector<poisson_ctx *> evict(size_t need, size_t keep)
     {
+        std::vector<poisson_ctx *> gone;
         while (!cache.empty()) {
             const bool over_budget = used + need > o.hbm_budget, over_count = cache.size() > keep;
             if (!over_budget && !over_count) break;
@@ -117,10 +119,11 @@ struct poisson_server {
             for (int q = 0; q < (int)cache.size(); ++q)
                 if (!cache[q].busy && (lru < 0 || cache[q].last < cache[lru].last)) lru = q;
             if (lru < 0) break;
-            poisson_destroy(cache[lru].ctx);
+            gone.push_back(cache[lru].ctx);
             used -= cache[lru].bytes;
             cache.erase(cache.begin() + lru);
         }
+        return gone;
     }
     ~poisson_server()
     {
@@ -134,12 +137,14 @@ void poisson_server::run_request(Request *r)
     std::string err;
     hipStream_t s = nullptr;
     poisson_ctx *keep = nullptr;  // set-up to cache after the solve
+    double setup_ms = 0.0, solve_ms = 0.0;  // published with the result, under mu
     try {
         IBM_HIP(hipSetDevice(o.device));
         IBM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         ibm_grid g{r->g.n[0], r->g.n[1], r->g.n[2], r->g.f[0].data(), r->g.f[1].data(), r->g.f[2].data()};
         const long long N = (long long)g.nx * g.ny * g.nz;
         poisson_ctx *ctx = r->ctx;
+        const auto ts = std::chrono::steady_clock::now();
         if (!ctx) {
             std::vector<ibm_body> bd;
             for (auto &b : r->bodies)
@@ -154,6 +159,8 @@ void poisson_server::run_request(Request *r)
             int e = poisson_setup(&g, flags.p, st, &r->opts, &bytes, &ctx);
             if (e) throw Error(e, ibm_last_error());
         }
+        if (!r->ctx) setup_ms = now_ms(ts);  // the temporaries' release included
+        const auto tv = std::chrono::steady_clock::now();
         std::unique_ptr<poisson_ctx, void (*)(poisson_ctx *)> cg(ctx, poisson_destroy);
         int64_t nun = 0;
         IBM_REQUIRE(poisson_level_info(ctx, nullptr, &nun, nullptr, nullptr) == IBM_OK, IBM_EINVAL, "level info");
@@ -165,6 +172,7 @@ void poisson_server::run_request(Request *r)
         r->x.resize(nt);
         IBM_HIP(hipMemcpyAsync(r->x.data(), dx.p, nt * 8, hipMemcpyDeviceToHost, s));
         IBM_HIP(hipStreamSynchronize(s));
+        solve_ms = now_ms(tv);
         if (o.cache_entries > 0) keep = cg.release();
     } catch (const Error &e) {
         rc = e.code;
@@ -175,12 +183,15 @@ void poisson_server::run_request(Request *r)
     }
     if (s) (void)hipStreamDestroy(s);
     if (rc != IBM_OK && getenv("IBM_LOG")) fprintf(stderr, "[ibm] request failed (%d): %s\n", rc, err.c_str());
-    std::lock_guard<std::mutex> lk(mu);
+    std::vector<poisson_ctx *> gone;
+    std::unique_lock<std::mutex> lk(mu);
     r->rc = rc;
     r->err = err;
     r->stats.status = rc;
     r->state = rc == IBM_OK || rc == IBM_ENOCONV ? IBM_REQ_DONE : IBM_REQ_FAILED;
     r->times.done_ms = now_ms(t0);
+    r->times.setup_ms = setup_ms;
+    r->times.solve_ms = solve_ms;
     if (r->ctx) {
         // a cached set-up: back to idle (its memory stays accounted), or gone
         // if the solve failed
@@ -197,12 +208,14 @@ void poisson_server::run_request(Request *r)
         e.bytes = r->footprint;  // stays accounted while cached
         e.last = ++tick;
         cache.push_back(std::move(e));
-        evict(0, (size_t)o.cache_entries);
+        gone = evict(0, (size_t)o.cache_entries);
     } else {
         used -= r->footprint;
     }
     --active;
     cv.notify_all();
+    lk.unlock();
+    for (poisson_ctx *c : gone) poisson_destroy(c);
 }
 
 void poisson_server::schedule()
@@ -244,8 +257,13 @@ void poisson_server::schedule()
             r->ctx = e->ctx;
             r->times.cache_hit = 1;
         } else {
-            evict(r->footprint, (size_t)o.cache_entries);
+            std::vector<poisson_ctx *> gone = evict(r->footprint, (size_t)o.cache_entries);
             used += r->footprint;
+            if (!gone.empty()) {
+                lk.unlock();
+                for (poisson_ctx *c : gone) poisson_destroy(c);
+                lk.lock();
+            }
         }
         ++active;
         r->state = IBM_REQ_RUNNING;
