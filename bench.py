@@ -117,7 +117,7 @@ def measured_traffic(workload_key):
         return None
 
 
-def serving_bench(P, rates, nreq, seed=5, slots=8, budget=64 << 30):
+def serving_bench(P, rates, nreq, seed=5, slots=16, budget=64 << 30):
     """Poisson arrivals of mixed-precision solve requests (grid edge
     log-uniform in [64, 384], cube or 2:1:1, 1-4 bodies, tol 1e-8) into the
     continuous-batching server; latency = done - submit on the server clock.
@@ -143,8 +143,8 @@ def serving_bench(P, rates, nreq, seed=5, slots=8, budget=64 << 30):
     while srv.poll(t, want_x=False)[0] == P.IBM_EAGAIN:
         time.sleep(0.001)
     out = []
-    for ri, rate in enumerate(rates):
-        reqs = make(10000 * (ri + 1), nreq)
+    for rate in rates:
+        reqs = make(10000 * int(rate), nreq)  # the same requests for a rate in every run
         arr = np.cumsum(np.random.default_rng(seed + int(rate)).exponential(1.0 / rate, nreq))
         pending, done = {}, []
         t0 = time.perf_counter()
@@ -330,6 +330,7 @@ def main():
     ap.add_argument("--no-ad", action="store_true", help="skip the advection-diffusion step measurement")
     ap.add_argument("--serve-rates", default="5,20,80,200", help="request arrival rates (req/s) of the serving sweep")
     ap.add_argument("--serve-requests", type=int, default=48, help="requests per arrival rate")
+    ap.add_argument("--serve-slots", type=int, default=16, help="concurrently active solves in the server")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with 3 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -438,7 +439,8 @@ def main():
         log("fp64: %.1f ms/solve, %d its; mixed speed-up %.2fx, rel error %.2e" % (ms64, s64.iterations,
                                                                                    ms64 / ms_per_step, err))
     if not args.no_serve:
-        out["serving"] = serving_bench(P, [float(r) for r in args.serve_rates.split(",")], args.serve_requests)
+        out["serving"] = serving_bench(P, [float(r) for r in args.serve_rates.split(",")], args.serve_requests,
+                                       slots=args.serve_slots)
     if not args.no_moving:
         out["moving"] = moving_bench(P)
     if not args.no_ad:
