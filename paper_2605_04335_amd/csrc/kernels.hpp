@@ -1324,11 +1324,10 @@ __device__ double tail_sum(double v)
 template <class Tc>
 __device__ void tail_sweep(const Lv &L, Tc *x, const Tc *b, double mu, int c, bool zero)
 {
-    const long long n = (long long)L.H * L.ny * L.nz;
-    for (long long q = threadIdx.x; q < n; q += blockDim.x) {
-        const int h = (int)(q % L.H);
-        const long long row = q / L.H;
-        const int j = (int)(row % L.ny), k = (int)(row / L.ny);
+    const int n = L.H * L.ny * L.nz;  // a tail level fits in LDS: 32-bit indices
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int h = q % L.H, row = q / L.H;
+        const int j = row % L.ny, k = row / L.ny;
         const long long s = (long long)c * L.Nh + q;
         const uint8_t f = L.f[s];
         const int i = 2 * h + ((c + j + k) & 1);
@@ -1346,6 +1345,77 @@ __device__ void tail_sweep(const Lv &L, Tc *x, const Tc *b, double mu, int c, bo
         st(x, s, dg > 0.0 ? (off - (ld(b, s) - mu)) / dg : 0.0);
     }
     __syncthreads();
+}
+
+// A coarsest level of at most 64 cells per colour runs its sweeps in one
+// wavefront: each lane keeps its cell's open-face neighbour offsets, face
+// coefficients, diagonal and b - mu in registers, and the half-sweeps are
+// separated by wavefront barriers instead of block barriers.  Same
+// operations, in the same order, as tail_sweep.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class Tc>
+__device__ void tail_coarsest_wave(const Lv &L, Tc *x, const Tc *b, double mu, int steps)
+{
+    const int lane = threadIdx.x & 63;
+    const int n = L.H * L.ny * L.nz;  // <= 64
+    int nb[2][6];
+    double cf[2][6], dg[2], bm[2];
+    bool act[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        act[c] = false;
+        dg[c] = bm[c] = 0.0;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            nb[c][t] = -1;
+            cf[c][t] = 0.0;
+        }
+        if (lane >= n) continue;
+        const int h = lane % L.H, row = lane / L.H, j = row % L.ny, k = row / L.ny;
+        const int s = c * (int)L.Nh + lane;
+        const uint8_t f = L.f[s];
+        const int i = 2 * h + ((c + j + k) & 1);
+        if (!(f & 1) || i >= L.nx) continue;
+        act[c] = true;
+        const int p = i & 1, o = (1 - c) * (int)L.Nh + L.H * (j + L.ny * k) + h;
+        const int pl = L.H * L.ny;
+        const uint8_t bit[6] = {CM_PX, CM_MX, CM_PY, CM_MY, CM_PZ, CM_MZ};
+        const int off[6] = {p, p - 1, L.H, -L.H, pl, -pl};
+        const double cv[6] = {L.cp[0][i], L.cm[0][i], L.cp[1][j], L.cm[1][j], L.cp[2][k], L.cm[2][k]};
+        double d = 0.0;
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+            if (f & bit[t]) {
+                nb[c][t] = o + off[t];
+                cf[c][t] = cv[t];
+                d += cv[t];
+            }
+        dg[c] = d;
+        bm[c] = ld(b, s) - mu;
+    }
+    for (int it = 0; it < steps; ++it) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (act[c]) {
+                double acc = 0.0;
+                if (it > 0 || c == 1) {
+#pragma unroll
+                    for (int t = 0; t < 6; ++t)
+                        if (nb[c][t] >= 0) acc += cf[c][t] * ld(x, nb[c][t]);
+                }
+                st(x, c * L.Nh + lane, dg[c] > 0.0 ? (acc - bm[c]) / dg[c] : 0.0);
+            } else if (it == 0 && lane < n) {
+                st(x, c * L.Nh + lane, 0.0);
+            }
+            wave_sync();
+        }
+    }
 }
 
 // view of tail level l whose mask lives in LDS
@@ -1381,6 +1451,11 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
         const double mu = mus[l];
         const bool last = l == T.n - 1;
         const int steps = last ? T.ncs : T.nu1;
+        if (last && (long long)L.H * L.ny * L.nz <= 64) {
+            if (threadIdx.x < 64) tail_coarsest_wave<Tc>(L, x, b, mu, steps);
+            __syncthreads();
+            break;
+        }
         for (int it = 0; it < steps; ++it) {
             tail_sweep<Tc>(L, x, b, mu, 0, it == 0);
             tail_sweep<Tc>(L, x, b, mu, 1, it == 0);
@@ -1390,13 +1465,12 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
         // storage precision), then its volume-weighted mean
         const Lv C = tail_lv(T, l + 1, smem);
         Tc *bc = (Tc *)(smem + T.t[l + 1].boff);
-        const long long nc = (long long)C.H * C.ny * C.nz;
-        for (long long q = threadIdx.x; q < 2 * nc; q += blockDim.x) {
+        const int nc = C.H * C.ny * C.nz;
+        for (int q = threadIdx.x; q < 2 * nc; q += blockDim.x) {
             const int cc = q >= nc ? 1 : 0;
-            const long long qq = q - cc * nc;
-            const int hc = (int)(qq % C.H);
-            const long long row = qq / C.H;
-            const int J = (int)(row % C.ny), K = (int)(row / C.ny);
+            const int qq = q - cc * nc;
+            const int hc = qq % C.H, row = qq / C.H;
+            const int J = row % C.ny, K = row / C.ny;
             double mub = mu;
             restrict_one<false, Tc, Tc, Tc>(L, C, -1, x, b, &mub, (const Tc *)nullptr, bc, cc, hc, J, K);
             const long long sc = (long long)cc * C.Nh + qq;
@@ -1404,13 +1478,12 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
         }
         __syncthreads();
         double part = 0.0;
-        for (long long q = threadIdx.x; q < 2 * nc; q += blockDim.x) {
+        for (int q = threadIdx.x; q < 2 * nc; q += blockDim.x) {
             if (!(C.f[q] & 1)) continue;
             const int cc = q >= nc ? 1 : 0;
-            const long long qq = q - cc * nc;
-            const int hc = (int)(qq % C.H);
-            const long long row = qq / C.H;
-            const int J = (int)(row % C.ny), K = (int)(row / C.ny);
+            const int qq = q - cc * nc;
+            const int hc = qq % C.H, row = qq / C.H;
+            const int J = row % C.ny, K = row / C.ny;
             const int I = 2 * hc + ((cc + J + K) & 1);
             part += C.w[0][I] * C.w[1][J] * C.w[2][K] * ld(bc, q);
         }
@@ -1422,13 +1495,12 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
         const Lv L = tail_lv(T, l, smem), C = tail_lv(T, l + 1, smem);
         Tc *x = (Tc *)(smem + T.t[l].xoff);
         const Tc *xc = (const Tc *)(smem + T.t[l + 1].xoff);
-        const long long n = (long long)L.H * L.ny * L.nz;
-        for (long long q = threadIdx.x; q < 2 * n; q += blockDim.x) {
+        const int n = L.H * L.ny * L.nz;
+        for (int q = threadIdx.x; q < 2 * n; q += blockDim.x) {
             const int c = q >= n ? 1 : 0;
-            const long long qq = q - c * n;
-            const int h = (int)(qq % L.H);
-            const long long row = qq / L.H;
-            prolong_one<false>(L, C, T.t[l].M, xc, x, c, h, (int)(row % L.ny), (int)(row / L.ny));
+            const int qq = q - c * n;
+            const int h = qq % L.H, row = qq / L.H;
+            prolong_one<false>(L, C, T.t[l].M, xc, x, c, h, row % L.ny, row / L.ny);
         }
         __syncthreads();
         const Tc *b = (const Tc *)(smem + T.t[l].boff);
