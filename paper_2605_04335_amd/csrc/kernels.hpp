@@ -1028,11 +1028,24 @@ __global__ void __launch_bounds__(TPB) k0_restrict_res(Lv F, Lv C, Geo Gc, long 
         };
         ldcol(2 * k0 - 1, 0);
         ldcol(2 * k0, 1);
+        const double wIJ = C.w[0][I] * C.w[1][J];
         for (int K = k0; K < k1; ++K) {
             ldcol(2 * K + 1, 2);
             ldcol(2 * K + 2, 3);
             // every load of the step is issued before any use: flags, RHS,
-            // the outer x and y neighbours of the 8 children
+            // the outer x and y neighbours of the 8 children, the z
+            // coefficients of the two fine planes and the coarse cell's mask
+            const long long sc = slot(C, (I + J + K) & 1, I >> 1, J, K);
+            const uint8_t fc = C.f[sc];
+            const double wK = C.w[2][K];
+            R czp[2], czm[2], wz[2];
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz) {
+                const int k = 2 * K + dz;
+                czp[dz] = (R)F.cp[2][k];  // zero at the walls
+                czm[dz] = (R)F.cm[2][k];
+                wz[dz] = (R)F.w[2][k];
+            }
             uint8_t fq[8];
             T bq[8], xq[8], yq[8];
 #pragma unroll
@@ -1066,21 +1079,20 @@ __global__ void __launch_bounds__(TPB) k0_restrict_res(Lv F, Lv C, Geo Gc, long 
                     const R xpy = dy ? yq[q] : v[o][1][1 + dz];
                     const R xmy = dy ? v[o][0][1 + dz] : yq[q];
                     const R xpz = v[o][dy][2 + dz], xmz = v[o][dy][dz];
-                    const R czp = (R)F.cp[2][k], czm = (R)F.cm[2][k];  // zero at the walls
-                    const R dg = cpx[dx] + cmx[dx] + cpy[dy] + cmy[dy] + czp + czm;
-                    const R n = cpx[dx] * xpx + cmx[dx] * xmx + cpy[dy] * xpy + cmy[dy] * xmy + czp * xpz +
-                                czm * xmz;
+                    const R dg = cpx[dx] + cmx[dx] + cpy[dy] + cmy[dy] + czp[dz] + czm[dz];
+                    const R n = cpx[dx] * xpx + cmx[dx] * xmx + cpy[dy] * xpy + cmy[dy] * xmy + czp[dz] * xpz +
+                                czm[dz] * xmz;
                     R bv = bq[q];
                     if (c * Nh + pl * kb + s == pin) bv -= snk;
                     r = bv - (n - dg * xv);
                 }
-                const R V = wx[dx] * wy[dy] * (R)F.w[2][k];
+                const R V = wx[dx] * wy[dy] * wz[dz];
                 sv += V;
                 svr += V * r;
             }
-            const long long sc = slot(C, (I + J + K) & 1, I >> 1, J, K);
-            st(bc, sc, sv > 0 ? (double)(svr / (R)(C.w[0][I] * C.w[1][J] * C.w[2][K])) : 0.0);
-            if (C.f[sc] & 1) a.v[0] += C.w[0][I] * C.w[1][J] * C.w[2][K] * ld(bc, sc);
+            const double vc = wIJ * wK;  // coarse cell volume
+            st(bc, sc, sv > 0 ? (double)(svr / (R)vc) : 0.0);
+            if (fc & 1) a.v[0] += vc * ld(bc, sc);
 #pragma unroll
             for (int c = 0; c < 2; ++c)
 #pragma unroll
