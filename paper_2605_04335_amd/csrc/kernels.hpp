@@ -419,12 +419,13 @@ __device__ __forceinline__ double cmask_sum_dg(const Lv &L, const Col0 &q, uint8
                                                double &cmx, double &cpy, double &cmy, double &czp, double &czm)
 {
     const bool t = k & 1;
+    const double zp = L.cp[2][k], zm = L.cm[2][k];  // loaded whatever the mask (no wait on it)
     cpx = (f & CM_PX) ? (t ? q.cpx[1] : q.cpx[0]) : 0.0;
     cmx = (f & CM_MX) ? (t ? q.cmx[1] : q.cmx[0]) : 0.0;
     cpy = (f & CM_PY) ? q.cpy : 0.0;
     cmy = (f & CM_MY) ? q.cmy : 0.0;
-    czp = (f & CM_PZ) ? L.cp[2][k] : 0.0;
-    czm = (f & CM_MZ) ? L.cm[2][k] : 0.0;
+    czp = (f & CM_PZ) ? zp : 0.0;
+    czm = (f & CM_MZ) ? zm : 0.0;
     return cpx + cmx + cpy + cmy + czp + czm;
 }
 
@@ -578,15 +579,33 @@ __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_
     const Col0 q = col0(L, c, h, j);
     const long long pl = (long long)L.H * L.ny;
     const long long col = h + (long long)L.H * j;
-    for (int k = k0; k < k1; ++k) {
-        const long long s = col + pl * k;
-        const bool t = k & 1;
-        const double dg = (t ? q.cpx[1] : q.cpx[0]) + (t ? q.cmx[1] : q.cmx[0]) + q.cpy + q.cmy + L.cp[2][k] + L.cm[2][k];
-        double b0 = ld(bc, s);
-        if (s == pin_s) b0 -= sink[0];
-        const uint8_t f = fc[s];
-        st(xc, s, (f & (F_SOLID | F_MGHOST)) ? 0.0 : -b0 / dg);
-        st(xo, s, 0.0);
+    const double snk = pin_s >= 0 ? sink[0] : 0.0;
+    // the RHS, masks and z coefficients of UZ planes are loaded before any is used
+    constexpr int UZ = 4;
+    for (int kb = k0; kb < k1; kb += UZ) {
+        double bv[UZ], zp[UZ], zm[UZ];
+        uint8_t fv[UZ];
+#pragma unroll
+        for (int u = 0; u < UZ; ++u) {
+            const int k = min(kb + u, k1 - 1);
+            const long long s = col + pl * k;
+            bv[u] = ld(bc, s);
+            fv[u] = fc[s];
+            zp[u] = L.cp[2][k];
+            zm[u] = L.cm[2][k];
+        }
+#pragma unroll
+        for (int u = 0; u < UZ; ++u) {
+            const int k = kb + u;
+            if (k >= k1) continue;
+            const long long s = col + pl * k;
+            const bool t = k & 1;
+            const double dg = (t ? q.cpx[1] : q.cpx[0]) + (t ? q.cmx[1] : q.cmx[0]) + q.cpy + q.cmy + zp[u] + zm[u];
+            double b0 = bv[u];
+            if (s == pin_s) b0 -= snk;
+            st(xc, s, (fv[u] & (F_SOLID | F_MGHOST)) ? 0.0 : -b0 / dg);
+            st(xo, s, 0.0);
+        }
     }
 }
 
@@ -949,6 +968,84 @@ __device__ __forceinline__ double restrict_one(const Lv &F, const Lv &C, long lo
     return (C.f[sc] & 1) ? VC * ld(bc, sc) : 0.0;
 }
 
+// restrict_one<false> for a coarse level in global memory, with the loads of
+// all 8 children issued before any is used: the 2x2x2 box, the 3 outer face
+// neighbours of each child (outside the level: the child itself, whose face
+// is closed in the mask), their RHS and masks, and the coefficients.  Same
+// arithmetic in the same order.
+template <class T, class TB, class TBc>
+__device__ __forceinline__ double restrict_box(const Lv &F, const Lv &C, const T *x, const TB *b, double mu, TBc *bc,
+                                               int cc, int hc, int J, int K)
+{
+    const long long sc = slot(C, cc, hc, J, K);
+    const int I = 2 * hc + ((cc + J + K) & 1);
+    if (I >= C.nx) {
+        st(bc, sc, 0.0);
+        return 0.0;
+    }
+    const uint8_t fC = C.f[sc];
+    const long long H = F.H, ny = F.ny;
+    T xb[8], xn[8][3];
+    uint8_t fb[8];
+    double bb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+        const int i = 2 * I + dx, j = 2 * J + dy, k = 2 * K + dz;
+        const int c = (dx + dy + dz) & 1;
+        const long long so = (long long)(1 - c) * F.Nh;
+        const long long s = (long long)c * F.Nh + I + H * (j + ny * k);
+        const int io = dx ? i + 1 : i - 1, jo = dy ? j + 1 : j - 1, ko = dz ? k + 1 : k - 1;
+        const long long sx = io >= 0 && io < F.nx ? so + (io >> 1) + H * (j + ny * k) : s;
+        const long long sy = jo >= 0 && jo < F.ny ? so + I + H * (jo + ny * k) : s;
+        const long long sz = ko >= 0 && ko < F.nz ? so + I + H * (j + ny * ko) : s;
+        xb[q] = x[s];
+        fb[q] = F.f[s];
+        bb[q] = ld(b, s);
+        xn[q][0] = x[sx];
+        xn[q][1] = x[sy];
+        xn[q][2] = x[sz];
+    }
+    double cpx[2], cmx[2], cpy[2], cmy[2], cpz[2], cmz[2], w0[2], w1[2], w2[2];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        cpx[d] = F.cp[0][2 * I + d];
+        cmx[d] = F.cm[0][2 * I + d];
+        cpy[d] = F.cp[1][2 * J + d];
+        cmy[d] = F.cm[1][2 * J + d];
+        cpz[d] = F.cp[2][2 * K + d];
+        cmz[d] = F.cm[2][2 * K + d];
+        w0[d] = F.w[0][2 * I + d];
+        w1[d] = F.w[1][2 * J + d];
+        w2[d] = F.w[2][2 * K + d];
+    }
+    double sv = 0.0, svr = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+        const uint8_t f = fb[q];
+        if (!(f & 1)) continue;
+        // face values in the order of nbsum: +x, -x, +y, -y, +z, -z
+        const double vpx = dx ? (double)xn[q][0] : (double)xb[q ^ 1], vmx = dx ? (double)xb[q ^ 1] : (double)xn[q][0];
+        const double vpy = dy ? (double)xn[q][1] : (double)xb[q ^ 2], vmy = dy ? (double)xb[q ^ 2] : (double)xn[q][1];
+        const double vpz = dz ? (double)xn[q][2] : (double)xb[q ^ 4], vmz = dz ? (double)xb[q ^ 4] : (double)xn[q][2];
+        double acc = 0.0, d = 0.0;
+        if (f & CM_PX) { acc += cpx[dx] * vpx; d += cpx[dx]; }
+        if (f & CM_MX) { acc += cmx[dx] * vmx; d += cmx[dx]; }
+        if (f & CM_PY) { acc += cpy[dy] * vpy; d += cpy[dy]; }
+        if (f & CM_MY) { acc += cmy[dy] * vmy; d += cmy[dy]; }
+        if (f & CM_PZ) { acc += cpz[dz] * vpz; d += cpz[dz]; }
+        if (f & CM_MZ) { acc += cmz[dz] * vmz; d += cmz[dz]; }
+        const double r = bb[q] - mu - (acc - d * (double)xb[q]);
+        const double V = w0[dx] * w1[dy] * w2[dz];
+        sv += V;
+        svr += V * r;
+    }
+    const double VC = C.w[0][I] * C.w[1][J] * C.w[2][K];
+    st(bc, sc, sv > 0.0 ? svr / VC : 0.0);
+    return (fC & 1) ? VC * ld(bc, sc) : 0.0;
+}
+
 // one thread per coarse cell in natural x order (Gc tiles I over C.nx), so a
 // wave reads the children's rows with unit stride
 template <bool FINE, class T, class TB, class TBc>
@@ -958,11 +1055,16 @@ __global__ void __launch_bounds__(TPB) k_restrict(Lv F, Lv C, Geo Gc, long long 
     Acc<1> a;
     a.v[0] = 0.0;
     int I, J, k0, k1;
-    if (geo_tile(Gc, I, J, k0, k1))
+    if (geo_tile(Gc, I, J, k0, k1)) {
+        const double mu = FINE ? 0.0 : (bsh ? bsh[0] : 0.0);
         for (int K = k0; K < k1; ++K) {
             const int cc = (I + J + K) & 1;
-            a.v[0] += restrict_one<FINE>(F, C, pin, x, b, bsh, rsp, bc, cc, I >> 1, J, K);
+            if constexpr (FINE)
+                a.v[0] += restrict_one<FINE>(F, C, pin, x, b, bsh, rsp, bc, cc, I >> 1, J, K);
+            else
+                a.v[0] += restrict_box(F, C, x, b, mu, bc, cc, I >> 1, J, K);
         }
+    }
     block_reduce<1>(a, part, 0, blockIdx.x);
 }
 
