@@ -1675,19 +1675,52 @@ __device__ __forceinline__ void st4(double *a, long long g, double (&o)[4])
 }
 
 // volumes of the 4 cells of a group (0 for inactive slots); e0 + 3 < 2 Nh
-__device__ __forceinline__ void group_volumes(const Lv &L, long long e0, double (&V)[4])
+// raw 4-wide group of a vector: loaded first, converted after every load of
+// the group has been issued
+template <class T>
+struct Raw4;
+template <>
+struct Raw4<float> {
+    float4 q;
+    __device__ __forceinline__ void load(const float *a, long long g) { q = reinterpret_cast<const float4 *>(a)[g]; }
+    __device__ __forceinline__ void get(double (&o)[4]) const
+    {
+        o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+    }
+};
+template <>
+struct Raw4<double> {
+    double2 q0, q1;
+    __device__ __forceinline__ void load(const double *a, long long g)
+    {
+        q0 = reinterpret_cast<const double2 *>(a)[2 * g];
+        q1 = reinterpret_cast<const double2 *>(a)[2 * g + 1];
+    }
+    __device__ __forceinline__ void get(double (&o)[4]) const
+    {
+        o[0] = q0.x; o[1] = q0.y; o[2] = q1.x; o[3] = q1.y;
+    }
+};
+
+// Cell volumes of the group of 4 slots from e0 (0 for inactive cells), with
+// the group's masks already loaded (fq) and every width loaded whatever the
+// mask (index clamped to the level), so that the loads of a group need not
+// wait for one another
+__device__ __forceinline__ void group_volumes_q(const Lv &L, long long e0, uchar4 fq, double (&V)[4])
 {
-    const uchar4 fq = *reinterpret_cast<const uchar4 *>(L.f + e0);
     const uint8_t f[4] = {fq.x, fq.y, fq.z, fq.w};
     int c, h, j, k, i;
     decode_slot(L, e0, c, h, j, k, i);
     if (h + 3 < L.H) {
-        const double wjk = L.w[1][j] * L.w[2][k];
         const int par = i & 1;
+        double w0[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w0[q] = L.w[0][min(2 * (h + q) + par, L.nx - 1)];
+        const double wjk = L.w[1][j] * L.w[2][k];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int iq = 2 * (h + q) + par;
-            V[q] = (iq < L.nx && active0(f[q])) ? L.w[0][iq] * wjk : 0.0;
+            V[q] = (iq < L.nx && active0(f[q])) ? w0[q] * wjk : 0.0;
         }
     } else {
 #pragma unroll
@@ -1712,16 +1745,26 @@ __global__ void __launch_bounds__(TPB) k_p_update4(Lv L, Walk W, long long ne, c
     WALK_BEGIN(W, g)
         const long long e0 = 4 * g;
         if (e0 + 3 < ne && (e0 + 3 < N2 || e0 >= N2)) {
+            // every load of the group goes out before any arithmetic (a group
+            // of membrane unknowns has no volumes: slot 0 stands in, unused)
+            const bool cells = e0 < N2;
+            const long long ev = cells ? e0 : 0;
+            const uchar4 fq = *reinterpret_cast<const uchar4 *>(L.f + ev);
+            Raw4<T> rq, pq, vq;
+            rq.load(r, g);
+            pq.load(pv, g);
+            vq.load(v, g);
+            double V[4];
+            group_volumes_q(L, ev, fq, V);
+            __builtin_amdgcn_sched_barrier(0);
             double rr[4], pp[4], vv[4];
-            ld4(r, g, rr);
-            ld4(pv, g, pp);
-            ld4(v, g, vv);
+            rq.get(rr);
+            pq.get(pp);
+            vq.get(vv);
 #pragma unroll
             for (int q = 0; q < 4; ++q) pp[q] = rr[q] + beta * (pp[q] - omega * vv[q]);
             st4(pv, g, pp);
-            if (e0 < N2) {
-                double V[4];
-                group_volumes(L, e0, V);
+            if (cells) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) a.v[0] += V[q] * pp[q];
             }
@@ -1751,15 +1794,22 @@ __global__ void __launch_bounds__(TPB) k_s_update4(Lv L, Walk W, long long ne, T
     WALK_BEGIN(W, g)
         const long long e0 = 4 * g;
         if (e0 + 3 < ne && (e0 + 3 < N2 || e0 >= N2)) {
+            const bool cells = e0 < N2;
+            const long long ev = cells ? e0 : 0;
+            const uchar4 fq = *reinterpret_cast<const uchar4 *>(L.f + ev);
+            Raw4<T> rq, vq;
+            rq.load(r, g);
+            vq.load(v, g);
+            double V[4];
+            group_volumes_q(L, ev, fq, V);
+            __builtin_amdgcn_sched_barrier(0);
             double rr[4], vv[4];
-            ld4(r, g, rr);
-            ld4(v, g, vv);
+            rq.get(rr);
+            vq.get(vv);
 #pragma unroll
             for (int q = 0; q < 4; ++q) rr[q] = rr[q] - alpha * vv[q];
             st4(r, g, rr);
-            if (e0 < N2) {
-                double V[4];
-                group_volumes(L, e0, V);
+            if (cells) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) a.v[0] += V[q] * rr[q];
             }
