@@ -418,6 +418,14 @@ def main():
         gbs = ts / (ms_per_step * 1e-3) / 1e9
         out["solve_hbm"] = {"bytes_per_solve": int(ts), "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    # whole solve against the compulsory-traffic model of the mixed form: per
+    # inner iteration 86 B/pt of FP32 Krylov kernels and two FP32/BF16
+    # V-cycles of 75 B/pt; per refinement step an FP64 residual and update of
+    # 41 B/pt
+    model = (236.0 * stm.iterations + 41.0 * stm.outer_steps) * N
+    gbm = model / (ms_per_step * 1e-3) / 1e9
+    out["solve_model"] = {"bytes_per_solve": int(model), "achieved": round(gbm, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(gbm / HBM_PEAK_GBS, 4)}
 
     if not args.no_fp64:
         del solm
