@@ -134,7 +134,7 @@ inline Geo make_geo(int H, int ny, int nz, int maxb = 8192)
     return g;
 }
 // tiles over cells in natural x order (nx instead of H): the restriction
-inline Geo make_geo_nat(int nx, int ny, int nz) { return make_geo(nx, ny, nz); }
+inline Geo make_geo_nat(int nx, int ny, int nz, int maxb = 8192) { return make_geo(nx, ny, nz, maxb); }
 
 // Tile of this block (XCD-contiguous remap); false for padding blocks.
 __device__ __forceinline__ bool geo_tile(const Geo &G, int &h, int &j, int &k0, int &k1)

@@ -77,8 +77,11 @@ void level_geometry(Level &L, const std::vector<double> *f, hipStream_t s)
     L.N = (long long)L.n[0] * L.n[1] * L.n[2];
     L.H = (L.n[0] + 1) / 2;
     L.Nh = (long long)L.H * L.n[1] * L.n[2];
-    L.geo = make_geo(L.H, L.n[1], L.n[2]);
-    L.geon = make_geo_nat(L.n[0], L.n[1], L.n[2]);
+    // levels below 2^26 cells take half the blocks (twice the planes per
+    // thread): their per-thread set-up is then spread over more planes
+    const int maxb = L.N < (1LL << 26) ? 4096 : 8192;
+    L.geo = make_geo(L.H, L.n[1], L.n[2], maxb);
+    L.geon = make_geo_nat(L.n[0], L.n[1], L.n[2], maxb);
     L.walk = make_walk(2 * L.Nh);
 }
 
