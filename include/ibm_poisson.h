@@ -22,6 +22,17 @@
  *     passed as void* (NULL = the null stream).
  *   - Every function returns 0 on success or a negative IBM_E* code; the
  *     message of the last failure on the calling thread is ibm_last_error().
+ *   - Device memory the library allocates for itself (contexts, stencils,
+ *     temporaries) comes from a per-device cache: a released block is not
+ *     returned with hipFree (which waits for the whole device) but reused
+ *     by later allocations of its size class once a background thread has
+ *     synchronised the device.  Blocks above 2 GiB bypass the cache.  The
+ *     environment variable IBM_MEM_CACHE_MB (default 16384) caps the cached
+ *     bytes per device; when hipMalloc fails, the cached blocks of that
+ *     device are freed and the allocation is tried once more.
+ *   - IBM_LOG set in the environment: refinement steps, fallbacks and
+ *     failed server requests are reported on stderr (IBM_LOG=2 adds every
+ *     BiCGSTAB iteration).
  */
 #ifndef IBM_POISSON_H
 #define IBM_POISSON_H
