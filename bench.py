@@ -331,6 +331,8 @@ def main():
     ap.add_argument("--serve-rates", default="5,20,80,200", help="request arrival rates (req/s) of the serving sweep")
     ap.add_argument("--serve-requests", type=int, default=48, help="requests per arrival rate")
     ap.add_argument("--serve-slots", type=int, default=16, help="concurrently active solves in the server")
+    ap.add_argument("--serve-small-budget-gb", type=int, default=8,
+                    help="HBM budget (GB) of a second run at the highest rate, where admission binds; 0: skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with 3 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -449,6 +451,12 @@ def main():
     if not args.no_serve:
         out["serving"] = serving_bench(P, [float(r) for r in args.serve_rates.split(",")], args.serve_requests,
                                        slots=args.serve_slots)
+        if args.serve_small_budget_gb > 0:
+            # the highest rate's requests again under a budget small enough
+            # that admission waits for memory
+            rate = max(float(r) for r in args.serve_rates.split(","))
+            out["serving_small_budget"] = serving_bench(P, [rate], args.serve_requests, slots=args.serve_slots,
+                                                        budget=args.serve_small_budget_gb << 30)
     if not args.no_moving:
         out["moving"] = moving_bench(P)
     if not args.no_ad:
