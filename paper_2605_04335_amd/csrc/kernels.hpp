@@ -297,31 +297,55 @@ __device__ __forceinline__ long long ghost_unknown(const Sp &S, int r)
     return r < S.ng ? (long long)S.rslot[r] : S.N2 + (r - S.ng);
 }
 
+// Sum of w x over the 8 stencil columns of ghost row r (a column < 0 is
+// absent).  The columns and weights are read first (16-byte loads), then
+// every value (an absent column reads unknown 0, unused), then the sum in
+// column order: one dependent step instead of one per column.
 template <class T>
 __device__ __forceinline__ double ghost_sum(const Sp &S, const T *x, int r)
 {
+    const int4 *c4 = reinterpret_cast<const int4 *>(S.rcol + 8 * (long long)r);
+    const double2 *w2 = reinterpret_cast<const double2 *>(S.rw + 8 * (long long)r);
+    int32_t gc[8];
+    double gw[8], xv[8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int4 q = c4[t];
+        gc[4 * t] = q.x; gc[4 * t + 1] = q.y; gc[4 * t + 2] = q.z; gc[4 * t + 3] = q.w;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double2 q = w2[t];
+        gw[2 * t] = q.x; gw[2 * t + 1] = q.y;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) xv[t] = ld(x, gc[t] >= 0 ? (long long)gc[t] : 0LL);
     double acc = 0.0;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const int32_t c = S.rcol[8 * r + m];
-        if (c >= 0) acc += S.rw[8 * r + m] * ld(x, c);
-    }
+    for (int t = 0; t < 8; ++t)
+        if (gc[t] >= 0) acc += gw[t] * xv[t];
     return acc;
 }
 
-// fluid row of membrane cell m: sum c (x_nb - xp) and its diagonal
+// fluid row of membrane cell m: sum c (x_nb - xp) and its diagonal; the six
+// neighbour values are loaded together (a wall reads unknown 0, unused)
 template <class T>
 __device__ __forceinline__ double mrow(const Lv &L, const Sp &S, const T *x, int m, double xp, double &s)
 {
     int c, h, j, k, i;
     decode_slot(L, S.mslot[m], c, h, j, k, i);
-    const int32_t *mc = S.mcol + 6 * m;
+    int32_t mc[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) mc[q] = S.mcol[6 * m + q];
     const double cf[6] = {L.cm[0][i], L.cp[0][i], L.cm[1][j], L.cp[1][j], L.cm[2][k], L.cp[2][k]};
+    double xv[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) xv[q] = ld(x, mc[q] >= 0 ? (long long)mc[q] : 0LL);
     double acc = 0.0;
     s = 0.0;
 #pragma unroll
     for (int q = 0; q < 6; ++q)
-        if (mc[q] >= 0) { acc += cf[q] * (ld(x, mc[q]) - xp); s += cf[q]; }
+        if (mc[q] >= 0) { acc += cf[q] * (xv[q] - xp); s += cf[q]; }
     return acc;
 }
 
@@ -882,8 +906,10 @@ __global__ void __launch_bounds__(TPB) k0_mscat(Sp S, T *x, int color, const dou
 template <class T>
 __global__ void __launch_bounds__(TPB) k0_gjac(Sp S, const T *x, const T *b, double *tmp)
 {
-    for (int r = blockIdx.x * TPB + threadIdx.x; r < S.nrows; r += gridDim.x * TPB)
-        tmp[r] = ghost_sum(S, x, r) - ld(b, ghost_unknown(S, r)) / S.rsG[r];
+    for (int r = blockIdx.x * TPB + threadIdx.x; r < S.nrows; r += gridDim.x * TPB) {
+        const double bv = ld(b, ghost_unknown(S, r)), sg = S.rsG[r];
+        tmp[r] = ghost_sum(S, x, r) - bv / sg;
+    }
 }
 
 template <class T>
