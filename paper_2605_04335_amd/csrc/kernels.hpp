@@ -1940,6 +1940,38 @@ __global__ void __launch_bounds__(TPB) k_copy_norm(Walk W, const TA *a, TB *b, T
     block_reduce<1>(s, part, 0, blockIdx.x);
 }
 
+// b = b2 = a (converted to TB) and the partial sums of the stored b^2, in
+// groups of 4 (the last group of the vector element by element); W walks
+// ceil(ne/4) groups
+template <class TA, class TB>
+__global__ void __launch_bounds__(TPB) k_copy_norm4(Walk W, long long ne, const TA *__restrict__ a,
+                                                    TB *__restrict__ b, TB *__restrict__ b2, double *part)
+{
+    Acc<1> s;
+    s.v[0] = 0.0;
+    WALK_BEGIN(W, g)
+        const long long e0 = 4 * g;
+        if (e0 + 3 < ne) {
+            Raw4<TA> aq;
+            aq.load(a, g);
+            double v[4];
+            aq.get(v);
+            st4(b, g, v);  // v now holds the stored values
+            st4(b2, g, v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s.v[0] += v[q] * v[q];
+        } else {
+            for (long long p = e0; p < ne; ++p) {
+                st(b, p, ld(a, p));
+                st(b2, p, ld(a, p));
+                const double v = ld(b, p);
+                s.v[0] += v * v;
+            }
+        }
+    WALK_END
+    block_reduce<1>(s, part, 0, blockIdx.x);
+}
+
 template <class T>
 __global__ void __launch_bounds__(TPB) k_add(Walk W, double *x, const T *d, double a = 1.0)
 {

@@ -512,21 +512,23 @@ void read_scalars(poisson_ctx &c, hipStream_t s)
     prof_harvest(c);
 }
 
-// Right-preconditioned BiCGSTAB on A y = rhs; y starts at zero.  Returns the
+// Right-preconditioned BiCGSTAB on A y = rhs; y starts at zero.  rhs may be
+// in a wider type than the vectors (the FP64 residual of a refinement step
+// feeding an FP32 inner solve: it is rounded on the way in).  Returns the
 // iteration count; *rc gets the status.
 constexpr int INNER_STALL = 12;
 
-template <class T, class TX>
-int bicgstab(poisson_ctx &c, const T *rhs, TX *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, double tol, int maxit,
+template <class T, class TX, class TR>
+int bicgstab(poisson_ctx &c, const TR *rhs, TX *y, T *r, T *rh, T *p, T *v, T *ph, T *sh, T *t, double tol, int maxit,
              bool true_check, hipGraphExec_t *graph, hipStream_t s, int *rc, double *relout)
 {
     const Walk &W = c.W0;
     k_fill<TX><<<W.nb, TPB, 0, s>>>(W, y, 0.0);
     k_fill<T><<<W.nb, TPB, 0, s>>>(W, p, 0.0);
     k_fill<T><<<W.nb, TPB, 0, s>>>(W, v, 0.0);
-    k_copy_norm<T, T><<<W.nb, TPB, 0, s>>>(W, rhs, r, rh, c.part.p);
+    k_copy_norm4<TR, T><<<c.W4.nb, TPB, 0, s>>>(c.W4, c.Nt, rhs, r, rh, c.part.p);
     IBM_LAUNCH_CHECK();
-    fin(c, W.nb, FIN_INIT, 0, 0.0, s);
+    fin(c, c.W4.nb, FIN_INIT, 0, 0.0, s);
     read_scalars(c, s);
     *rc = IBM_ENOCONV;
     if (c.hsc[S_BN2] == 0.0) {
@@ -584,19 +586,23 @@ int bicgstab(poisson_ctx &c, const T *rhs, TX *y, T *r, T *rh, T *p, T *v, T *ph
                     c.hsc[S_ALPHA], c.hsc[S_OMEGA], c.hsc[S_SINKP], c.hsc[S_SINKS]);
         if (st >= 2.0 || !std::isfinite(rel)) { *rc = IBM_EBREAKDOWN; break; }
         if (rel <= tol) {
-            if constexpr (!std::is_same<T, TX>::value) { *rc = IBM_OK; break; }  // inner solves: no true check
-            if (!true_check) { *rc = IBM_OK; break; }
-            int np = launch_apply<T>(c, M_PINNED, true, 2, (const T *)y, t, rhs, nullptr, rh, nullptr, s);
-            k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
-            read_scalars(c, s);
-            double trel = std::sqrt(c.hsc[S_TMP] / c.hsc[S_BN2]);
-            rel = trel;
-            if (trel <= tol) { *rc = IBM_OK; break; }
-            // residual replacement
-            k_copy<T, T><<<W.nb, TPB, 0, s>>>(W, t, r);
-            k_dot2<T><<<W.nb, TPB, 0, s>>>(W, rh, r, c.part.p, PSTRIDE);
-            fin(c, W.nb, FIN_REPLACE, 0, 0.0, s);
-            continue;
+            if constexpr (!std::is_same<T, TX>::value || !std::is_same<TR, T>::value) {
+                *rc = IBM_OK;  // inner solves: no true check
+                break;
+            } else {
+                if (!true_check) { *rc = IBM_OK; break; }
+                int np = launch_apply<T>(c, M_PINNED, true, 2, (const T *)y, t, rhs, nullptr, rh, nullptr, s);
+                k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
+                read_scalars(c, s);
+                double trel = std::sqrt(c.hsc[S_TMP] / c.hsc[S_BN2]);
+                rel = trel;
+                if (trel <= tol) { *rc = IBM_OK; break; }
+                // residual replacement
+                k_copy<T, T><<<W.nb, TPB, 0, s>>>(W, t, r);
+                k_dot2<T><<<W.nb, TPB, 0, s>>>(W, rh, r, c.part.p, PSTRIDE);
+                fin(c, W.nb, FIN_REPLACE, 0, 0.0, s);
+                continue;
+            }
         }
         if constexpr (!std::is_same<T, TX>::value) {
             if (rel < 0.5 * mark) {
@@ -1091,15 +1097,15 @@ int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s, bool warm = 
             }
             if (outer == o.max_outer) { rc = IBM_ENOCONV; break; }
             prev = rel;
-            // inner FP32 solve of A d = r64 (the inner residual vector starts as r64);
-            // it asks only for the reduction still needed, never less than inner_tol
-            k_copy<double, float><<<W.nb, TPB, 0, s>>>(W, c.r.p, c.fr.p);
-            IBM_LAUNCH_CHECK();
+            // inner FP32 solve of A d = r64 (the inner residual vector starts as r64
+            // rounded to FP32); it asks only for the reduction still needed,
+            // never less than inner_tol
             int irc;
             double irel;
             const double itol = std::max(o.inner_tol, 0.5 * o.tol / rel);
-            const int n_in = bicgstab<float, double>(c, c.fr.p, c.d64.p, c.fr.p, c.frh.p, c.fp.p, c.fv.p, c.fph.p, c.fsh.p,
-                                             c.ft.p, itol, o.max_iter, false, &c.g32, s, &irc, &irel);
+            const int n_in = bicgstab<float, double>(c, (const double *)c.r.p, c.d64.p, c.fr.p, c.frh.p, c.fp.p, c.fv.p,
+                                                     c.fph.p, c.fsh.p, c.ft.p, itol, o.max_iter, false, &c.g32, s,
+                                                     &irc, &irel);
             its += n_in;
             if (log_enabled())
                 fprintf(stderr, "[ibm] outer %d: rel %.3e, inner tol %.1e: %d iterations to %.2e (rc %d)\n", outer, rel,
