@@ -135,6 +135,10 @@ __device__ V3 closest_on_triangle(V3 p, V3 a, V3 b, V3 c)
     return q;
 }
 
+// triangles of a body are grouped in runs of TGROUP consecutive triangles
+// (mesh order) with one box per run
+constexpr int TGROUP = 32;
+
 struct Tris {
     const double *v;    // [nt*9] vertex coordinates
     const double *box;  // [nt*6] min xyz, max xyz
@@ -142,6 +146,8 @@ struct Tris {
     const double *bbox; // [nb*6] per-body boxes
     const int *bfirst;  // [nb+1] first triangle of each body
     const int *bkind;   // [nb]
+    const double *gbox; // [ng*6] boxes of the triangle runs
+    const int *gfirst;  // [nb+1] first run of each body
     int nb;
 };
 
@@ -159,6 +165,16 @@ __device__ __forceinline__ double box_lb(const double *bx, V3 p)
     e = p.x < bx[0] ? bx[0] - p.x : (p.x > bx[3] ? p.x - bx[3] : 0.0); s += e * e;
     e = p.y < bx[1] ? bx[1] - p.y : (p.y > bx[4] ? p.y - bx[4] : 0.0); s += e * e;
     e = p.z < bx[2] ? bx[2] - p.z : (p.z > bx[5] ? p.z - bx[5] : 0.0); s += e * e;
+    return s;
+}
+
+// the largest squared distance from p to a point of the box
+__device__ __forceinline__ double box_ub(const double *bx, V3 p)
+{
+    double e, s = 0.0;
+    e = fmax(fabs(p.x - bx[0]), fabs(p.x - bx[3])); s += e * e;
+    e = fmax(fabs(p.y - bx[1]), fabs(p.y - bx[4])); s += e * e;
+    e = fmax(fabs(p.z - bx[2]), fabs(p.z - bx[5])); s += e * e;
     return s;
 }
 
@@ -202,18 +218,35 @@ __global__ void __launch_bounds__(64) k_stencil(Tris T, GridD G, const uint8_t *
     const int ci = cell % nx, cj = (cell / nx) % ny, ck = cell / (nx * ny);
     const V3 P = {G.c[0][ci], G.c[1][cj], G.c[2][ck]};
     const int want = mem ? 1 : 0;
+    // A bound on the nearest squared distance before the search: the
+    // smallest farthest-point distance of any run box (every run holds a
+    // triangle at most that far), with a relative margin far above rounding.
+    // Runs, and then triangles, whose box lies farther than the bound or the
+    // best distance so far are skipped; the rest are visited in triangle
+    // order with the same strict comparison as a plain scan, so the chosen
+    // triangle (the first of the nearest) is the plain scan's.
+    double ub = INFINITY;
+    for (int b = 0; b < T.nb; ++b) {
+        if (T.bkind[b] != want) continue;
+        for (int g = T.gfirst[b]; g < T.gfirst[b + 1]; ++g) ub = fmin(ub, box_ub(T.gbox + 6 * g, P));
+    }
+    ub *= 1.0 + 1e-9;
     double best = INFINITY;
     V3 BI = {0, 0, 0};
     int bt = -1;
     for (int b = 0; b < T.nb; ++b) {
         if (T.bkind[b] != want) continue;
-        if (box_lb(T.bbox + 6 * b, P) > best) continue;
-        for (int t = T.bfirst[b]; t < T.bfirst[b + 1]; ++t) {
-            if (box_lb(T.box + 6 * t, P) > best) continue;
-            const double *tv = T.v + 9 * t;
-            V3 q = closest_on_triangle(P, {tv[0], tv[1], tv[2]}, {tv[3], tv[4], tv[5]}, {tv[6], tv[7], tv[8]});
-            double d2 = (q.x - P.x) * (q.x - P.x) + (q.y - P.y) * (q.y - P.y) + (q.z - P.z) * (q.z - P.z);
-            if (d2 < best) { best = d2; bt = t; BI = q; }
+        if (box_lb(T.bbox + 6 * b, P) > fmin(best, ub)) continue;
+        for (int g = T.gfirst[b]; g < T.gfirst[b + 1]; ++g) {
+            if (box_lb(T.gbox + 6 * g, P) > fmin(best, ub)) continue;
+            const int t0 = T.bfirst[b] + (g - T.gfirst[b]) * TGROUP, t1 = min(t0 + TGROUP, T.bfirst[b + 1]);
+            for (int t = t0; t < t1; ++t) {
+                if (box_lb(T.box + 6 * t, P) > fmin(best, ub)) continue;
+                const double *tv = T.v + 9 * t;
+                V3 q = closest_on_triangle(P, {tv[0], tv[1], tv[2]}, {tv[3], tv[4], tv[5]}, {tv[6], tv[7], tv[8]});
+                double d2 = (q.x - P.x) * (q.x - P.x) + (q.y - P.y) * (q.y - P.y) + (q.z - P.z) * (q.z - P.z);
+                if (d2 < best) { best = d2; bt = t; BI = q; }
+            }
         }
     }
     uint8_t fl = 0;
@@ -463,9 +496,10 @@ void build_stencils(const ibm_grid *grid, const ibm_body *bodies, int n_body, co
             }
             G.hmin = hmin;
             // triangles, flattened in (body, triangle) order
-            std::vector<double> tv, tb, bb;
-            std::vector<int> tk, bf, bk;
+            std::vector<double> tv, tb, bb, gbx;
+            std::vector<int> tk, bf, bk, gf;
             bf.push_back(0);
+            gf.push_back(0);
             for (int b = 0; b < n_body; ++b) {
                 const ibm_body &B = bodies[b];
                 IBM_REQUIRE(B.vert && B.tri && B.n_tri > 0, IBM_EINVAL, "empty body");
@@ -490,12 +524,24 @@ void build_stencils(const ibm_grid *grid, const ibm_body *bodies, int n_body, co
                 for (int d = 0; d < 3; ++d) bb.push_back(hi[d]);
                 bk.push_back(B.kind);
                 bf.push_back(bf.back() + B.n_tri);
+                // boxes of the runs of TGROUP consecutive triangles
+                for (int t0 = bf[b]; t0 < bf[b + 1]; t0 += TGROUP) {
+                    double glo[3] = {1e300, 1e300, 1e300}, ghi[3] = {-1e300, -1e300, -1e300};
+                    for (int t = t0; t < std::min(t0 + TGROUP, bf[b + 1]); ++t)
+                        for (int d = 0; d < 3; ++d) {
+                            glo[d] = std::min(glo[d], tb[6 * (size_t)t + d]);
+                            ghi[d] = std::max(ghi[d], tb[6 * (size_t)t + 3 + d]);
+                        }
+                    for (int d = 0; d < 3; ++d) gbx.push_back(glo[d]);
+                    for (int d = 0; d < 3; ++d) gbx.push_back(ghi[d]);
+                }
+                gf.push_back((int)(gbx.size() / 6));
             }
-            DBuf<double> dtv, dtb, dbb;
-            DBuf<int> dtk, dbf, dbk;
-            upload(dtv, tv, s); upload(dtb, tb, s); upload(dbb, bb, s);
-            upload(dtk, tk, s); upload(dbf, bf, s); upload(dbk, bk, s);
-            Tris T{dtv.p, dtb.p, dtk.p, dbb.p, dbf.p, dbk.p, n_body};
+            DBuf<double> dtv, dtb, dbb, dgb;
+            DBuf<int> dtk, dbf, dbk, dgf;
+            upload(dtv, tv, s); upload(dtb, tb, s); upload(dbb, bb, s); upload(dgb, gbx, s);
+            upload(dtk, tk, s); upload(dbf, bf, s); upload(dbk, bk, s); upload(dgf, gf, s);
+            Tris T{dtv.p, dtb.p, dtk.p, dbb.p, dbf.p, dbk.p, dgb.p, dgf.p, n_body};
             RowOut O{S->col.p, S->w.p, S->sG.p, S->dlb.p, S->geo.p, S->rfl.p};
             k_stencil<<<cdiv(rows, 64), 64, 0, s>>>(T, G, flags, S->cell.p, (int)S->ng, (int)rows, S->cell.p + S->ng,
                                                    (int)S->nm, N, bc, O);
