@@ -148,6 +148,15 @@ def stencils(xf, yf, zf, bodies, flags, bc: str = "neumann") -> Stencils:
     return Stencils(gcell, mcell, mg_of, col[:nr], w[:nr], sG[:nr], dlb[:nr], rfl[:nr], geo[:nr], box[:nr])
 
 
+def closest_point(p, a, b, c) -> np.ndarray:
+    """Closest point of triangle abc to p: the routine that picks each ghost
+    row's boundary intercept (Sec. 2.5, module 2)."""
+    q = np.zeros(3)
+    args = [_f64(v) for v in (p, a, b, c)]
+    lib().orc_closest_point(*[_p(v) for v in args], _p(q))
+    return q
+
+
 def _sys_args(xf, yf, zf, flags, st: Stencils):
     rows = st.row_cell
     col = np.ascontiguousarray(st.col, dtype=np.int32)

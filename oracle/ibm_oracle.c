@@ -338,6 +338,14 @@ static void closest_on_tri(const double *p, const double *a, const double *b, co
 #undef DOT
 }
 
+/* The same routine for the tests, which pin it against an independent
+ * construction (plane projection with barycentric coordinates, else the
+ * nearest clamped edge projection). */
+void orc_closest_point(const double *p, const double *a, const double *b, const double *c, double *q)
+{
+    closest_on_tri(p, a, b, c, q);
+}
+
 /* largest i <= n-2 with c[i] <= x, for x already clamped into [c0, c_{n-1}] */
 static int box_index(const double *c, int n, double x)
 {

@@ -4,7 +4,10 @@ Nothing here shares code with the oracle's C file or with the HIP library:
   * brute-force ray parity with exact integers and Fractions (intercepts
     computed explicitly from the plane equation),
   * a scipy.sparse assembler of the pinned ghost-cell system,
-  * closed-form solutions of the discrete Neumann problem.
+  * closed-form solutions of the discrete Neumann problem,
+  * closest points on triangles by plane projection and barycentric
+    coordinates, else the nearest clamped edge projection (a construction
+    unlike the Voronoi-region walk the oracle and the library use).
 """
 from __future__ import annotations
 
@@ -269,3 +272,76 @@ def assemble_masked_box(xf, yf, zf, closed_faces, pin=0):
                 else:
                     rows.append(p); cols.append(p); vals.append(-diag)
     return sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
+
+
+def closest_points_on_triangles(p, A, B, C):
+    """Closest point of each triangle (A[t], B[t], C[t]) to the point p, and
+    its squared distance.
+
+    The orthogonal projection of p onto the triangle's plane is kept when its
+    barycentric coordinates, from the 2x2 Gram system of the edges AB and AC,
+    are all non-negative; otherwise the closest point lies on the boundary
+    and is the nearest of the three projections of p onto the edge segments,
+    clamped to the segment.  Returns (Q[T, 3], d2[T], feature[T]) with
+    feature 0 for the face, 1-3 for the edges AB, BC, CA, 4-6 for the
+    vertices A, B, C."""
+    p = np.asarray(p, dtype=np.float64)
+    A, B, C = (np.atleast_2d(np.asarray(v, dtype=np.float64)) for v in (A, B, C))
+    e0, e1, v = B - A, C - A, p[None, :] - A
+    d00 = np.sum(e0 * e0, 1)
+    d01 = np.sum(e0 * e1, 1)
+    d11 = np.sum(e1 * e1, 1)
+    d20 = np.sum(v * e0, 1)
+    d21 = np.sum(v * e1, 1)
+    den = d00 * d11 - d01 * d01
+    s = (d11 * d20 - d01 * d21) / den
+    t = (d00 * d21 - d01 * d20) / den
+    inside = (s >= 0) & (t >= 0) & (s + t <= 1)
+    proj = A + s[:, None] * e0 + t[:, None] * e1
+    best_q = np.empty_like(A)
+    best_d = np.full(len(A), np.inf)
+    feat = np.zeros(len(A), dtype=np.int64)
+    for k, (U, V) in enumerate(((A, B), (B, C), (C, A))):
+        e = V - U
+        u = np.clip(np.sum((p[None, :] - U) * e, 1) / np.sum(e * e, 1), 0.0, 1.0)
+        q = U + u[:, None] * e
+        d = np.sum((q - p[None, :]) ** 2, 1)
+        better = d < best_d
+        best_q[better] = q[better]
+        best_d[better] = d[better]
+        # a clamped parameter puts the point on a vertex: the segment's start or end
+        fk = np.where(u <= 0.0, 4 + k, np.where(u >= 1.0, 4 + (k + 1) % 3, 1 + k))
+        feat[better] = fk[better]
+    dproj = np.sum((proj - p[None, :]) ** 2, 1)
+    Q = np.where(inside[:, None], proj, best_q)
+    d2 = np.where(inside, dproj, best_d)
+    feat = np.where(inside, 0, feat)
+    return Q, d2, feat
+
+
+def cell_centre_points(xf, yf, zf, cells):
+    """Centres of cells given by natural index (x fastest)."""
+    cs = [centres(xf), centres(yf), centres(zf)]
+    nx, ny = len(cs[0]), len(cs[1])
+    cells = np.asarray(cells, dtype=np.int64)
+    return np.stack([cs[0][cells % nx], cs[1][(cells // nx) % ny], cs[2][cells // (nx * ny)]], 1)
+
+
+def nearest_surface_points(G, bodies, kind):
+    """For each point of G, the closest point over every triangle of the bodies
+    of the given kind (0 closed, 1 membrane), ties broken by the lowest
+    triangle index in (body, triangle) order.  Returns (Q[n, 3], d2[n],
+    tri[n], ties[n]): ties counts the triangles within a relative 1e-12 of the
+    minimum squared distance."""
+    tris = [np.asarray(b.verts, dtype=np.float64)[np.asarray(b.tris)] for b in bodies if b.kind == kind]
+    T = np.concatenate(tris, 0)
+    out_q = np.zeros((len(G), 3))
+    out_d = np.zeros(len(G))
+    out_t = np.zeros(len(G), dtype=np.int64)
+    ties = np.zeros(len(G), dtype=np.int64)
+    for n, g in enumerate(np.asarray(G, dtype=np.float64)):
+        Q, d2, _ = closest_points_on_triangles(g, T[:, 0], T[:, 1], T[:, 2])
+        t = int(np.argmin(d2))  # first index of the minimum
+        out_q[n], out_d[n], out_t[n] = Q[t], d2[t], t
+        ties[n] = int(np.sum(d2 <= d2[t] * (1 + 1e-12)))
+    return out_q, out_d, out_t, ties

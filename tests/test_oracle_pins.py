@@ -2,8 +2,9 @@
 
 P1 closed-form discrete eigenvector, P2 second-order convergence, P3 direct
 solve of an independently assembled matrix, P4 invariants, P5 flat-wall
-equivalence, P6 exact classification, P7 ghost geometry, P10 manufactured
-discrete solution.
+equivalence, P6 exact classification, P7 ghost geometry (with the boundary
+intercept pinned by an independent closest-point construction), P10
+manufactured discrete solution.
 """
 import math
 
@@ -304,6 +305,115 @@ def test_p7_ghost_geometry_sphere():
     # ghost cells are inside the sphere, within one cell diagonal of the surface
     rg = np.linalg.norm(G - 0.5, axis=1)
     assert np.all(rg < 0.25 + 1e-9) and np.all(rg > 0.25 - math.sqrt(3) / n)
+
+
+# ---------------------------------------------------------------- P7b: boundary intercept
+# The ghost row's boundary intercept (Sec. 2.5, module 2) is the closest point
+# on the owning kind's triangles, ties to the lowest triangle index.  The
+# oracle walks Voronoi regions; refpy projects onto the plane with
+# barycentric coordinates, else onto the clamped edges.
+
+def _region_points(rng, A, B, C, n):
+    """Points around a triangle: its plane, far above and below, and wide."""
+    ctr = (A + B + C) / 3.0
+    size = max(np.linalg.norm(B - A), np.linalg.norm(C - A), np.linalg.norm(C - B))
+    return ctr + size * rng.uniform(-1.5, 1.5, (n, 3))
+
+
+def test_p7_closest_point_all_voronoi_regions():
+    rng = np.random.default_rng(71)
+    tris = [rng.uniform(0, 1, (3, 3)) for _ in range(24)]
+    # a sliver, an obtuse and a right triangle as well
+    tris.append(np.array([[0.1, 0.2, 0.3], [0.9, 0.21, 0.3], [0.5, 0.2004, 0.31]]))
+    tris.append(np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.5, 0.05, 0.0]]))
+    tris.append(np.array([[0.0, 0.0, 0.0], [0.25, 0.0, 0.0], [0.0, 0.125, 0.0]]))
+    seen = set()
+    worst = 0.0
+    for T in tris:
+        A, B, C = T
+        pts = _region_points(rng, A, B, C, 300)
+        # points exactly at the vertices, on the edges and inside
+        pts = np.concatenate([pts, T, [0.5 * (A + B), 0.5 * (B + C), 0.25 * (A + B) + 0.5 * C]])
+        for p in pts:
+            Q, d2, feat = refpy.closest_points_on_triangles(p, A[None], B[None], C[None])
+            q = oracle.closest_point(p, A, B, C)
+            seen.add(int(feat[0]))
+            worst = max(worst, float(np.max(np.abs(q - Q[0]))))
+    assert seen == set(range(7)), seen
+    assert worst < 1e-12, worst
+
+
+def _check_intercepts(p, bodies_kind_rows):
+    """Every ghost row's BI against the independent nearest-surface search."""
+    S = setup_problem(p.xf, p.yf, p.zf, p.bodies)
+    st = S.st
+    ok_rows = 0
+    for kind, rows, cells in bodies_kind_rows(st):
+        keep = (st.rfl[rows] & 4) == 0  # a ghost on the surface uses its face normal instead
+        rows, cells = rows[keep], cells[keep]
+        if not len(rows):
+            continue
+        G = refpy.cell_centre_points(p.xf, p.yf, p.zf, cells)
+        Q, d2, tri, ties = refpy.nearest_surface_points(G, p.bodies, kind)
+        BI, dist = st.geo[rows, 0:3], st.geo[rows, 11]
+        assert np.allclose(dist ** 2, d2, rtol=1e-12, atol=0.0)
+        single = ties == 1
+        assert np.max(np.abs(BI[single] - Q[single]), initial=0.0) < 1e-12
+        # tied triangles: BI is the closest point of one of them
+        T = np.concatenate([np.asarray(b.verts)[np.asarray(b.tris)] for b in p.bodies if b.kind == kind], 0)
+        for n in np.nonzero(~single)[0]:
+            Qa, da, _ = refpy.closest_points_on_triangles(G[n], T[:, 0], T[:, 1], T[:, 2])
+            cand = np.nonzero(da <= d2[n] * (1 + 1e-12))[0]
+            assert np.min(np.max(np.abs(Qa[cand] - BI[n]), axis=1)) < 1e-12
+        ok_rows += len(rows)
+    return ok_rows
+
+
+def _closed_rows(st):
+    yield 0, np.arange(st.ng), st.gcell
+
+
+def _all_rows(st):
+    yield 0, np.arange(st.ng), st.gcell
+    yield 1, st.ng + np.arange(st.nm), st.mcell
+
+
+@pytest.mark.parametrize("name", ["c1", "membrane_64", "sphere_plate_48"])
+def test_p7_boundary_intercept_is_nearest_surface_point(name):
+    if name == "c1":
+        p = W.sphere_case(32)
+    elif name == "membrane_64":
+        p = W.membrane_case(64, nc=40, ns=120)
+    else:
+        p = W.Problem(name, W.uniform_faces(48), W.uniform_faces(48), W.uniform_faces(48),
+                      [W.sphere((0.3, 0.3, 0.5), 0.15), W.plate((0.7, 0.6, 0.5), 0.2, 0.5, 20, 50, 0.03, 0.4)])
+    assert _check_intercepts(p, _all_rows) > 100
+
+
+@pytest.mark.parametrize("top_first", [False, True])
+def test_p7_exact_ties_take_the_lowest_triangle_index(top_first):
+    """A one-cell-thick slab whose ghost centres sit exactly midway between
+    its lower and upper faces (dyadic coordinates: the distances are exact
+    and equal): BI lies on the face whose triangles come first."""
+    n = 16
+    body = W.box((0.25, 0.25, 7 / 16), (0.75, 0.75, 8 / 16))
+    if top_first:  # the +z face's two triangles first, the rest in their order
+        order = [10, 11] + [t for t in range(12) if t not in (10, 11)]
+        body = W.Body(body.verts, body.tris[order], body.kind)
+    f = W.uniform_faces(n)
+    p = W.Problem("slab", f, f, f, [body])
+    S = setup_problem(p.xf, p.yf, p.zf, p.bodies)
+    st = S.st
+    G = refpy.cell_centre_points(p.xf, p.yf, p.zf, st.gcell)
+    assert np.all(G[:, 2] == 7.5 / 16)
+    Q, d2, tri, ties = refpy.nearest_surface_points(G, p.bodies, 0)
+    assert np.all(ties >= 2)  # every ghost is tied between at least two faces
+    BI = st.geo[:, 0:3]
+    assert np.array_equal(BI, Q)  # dyadic: the lowest tied triangle's point, exactly
+    # interior ghosts (away from the side faces) land on the first-listed z face
+    inner = (np.abs(G[:, 0] - 0.5) < 0.2) & (np.abs(G[:, 1] - 0.5) < 0.2)
+    assert inner.sum() >= 16
+    assert np.all(BI[inner, 2] == (8 / 16 if top_first else 7 / 16))
 
 
 # ---------------------------------------------------------------- P10
