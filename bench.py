@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: multigrid-preconditioned BiCGSTAB pressure solve on one MI355X.
 
-A step is one whole PPE solve (RHS assembly, pinned MG-BiCGSTAB to the
-tolerance, gauge) of the configured workload with its inputs resident in
-HBM.  Default workload: 512^3 tanh-stretched grid (ratio 1.05) around a
-cambered zero-thickness plate (40k triangles), uniform-noise RHS, mixed
-precision (FP32 V-cycle and inner BiCGSTAB with BF16 coarse right-hand
-sides inside FP64 iterative refinement) to 1e-8 relative residual; the plain
-FP64 solve of the same system is timed beside it.
+A step is one whole PPE solve (RHS assembly, pinned MG-BiCGSTAB to a 1e-8
+relative residual, gauge) of the configured workload with its inputs
+resident in HBM.  The headline is the paper's precision, FP64 throughout
+(Sec. 3 states every figure in double precision).  Default workload: 512^3
+tanh-stretched grid (ratio 1.05) around a cambered zero-thickness plate (40k
+triangles) with ghost unknowns on both sides, uniform-noise RHS.
+
+Beside the headline: the mixed form (FP32 V-cycle and inner BiCGSTAB with
+BF16 coarse right-hand sides inside FP64 iterative refinement) on the same
+system, the error of both against a stored sample of the FP64 oracle's
+solution and the speed-up at equal accuracy; the 1024^3, 20-sphere case in
+both forms; the device's streaming ceiling; the serving sweep; the
+moving-body and advection-diffusion steps; and the oracle timed on the host.
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 is refused.
 """
@@ -27,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MG-BiCGSTAB pressure solve Mpts/s to 1e-8 resid, % HBM peak; serve p50/p99"
 HBM_PEAK_GBS = 8000.0
+KEYS = {"c3": "membrane512", "c2": "spheroids256", "c4": "spheres1024", "c1": "sphere32"}
 
 
 def log(*a):
@@ -37,23 +44,85 @@ def make_problem(cfg):
     from paper_2605_04335_amd import workloads as W
     if cfg == "c3":
         p = W.membrane_case(512)
-        p.tol = 1e-8
-        return p, "membrane plate 512^3 tanh-stretched, 40k triangles, noise RHS, mixed MG-BiCGSTAB to 1e-8"
-    if cfg == "c2":
+        desc = "membrane plate 512^3 tanh-stretched, 40k triangles, noise RHS, MG-BiCGSTAB to 1e-8"
+    elif cfg == "c2":
         p = W.sphere_ellipsoid_case(256)
-        p.tol = 1e-8
-        p.mixed = True
-        return p, "sphere+ellipsoid 256^3 tanh-stretched, noise RHS, mixed MG-BiCGSTAB to 1e-8"
-    if cfg == "c4":
+        desc = "sphere+ellipsoid 256^3 tanh-stretched, noise RHS, MG-BiCGSTAB to 1e-8"
+    elif cfg == "c4":
         p = W.spheres_case(1024)
-        p.mixed = True
-        return p, "20 spheres 1024^3 uniform, Gaussian-bump RHS, mixed MG-BiCGSTAB to 1e-8"
-    if cfg == "c1":
+        desc = "20 spheres 1024^3 uniform, Gaussian-bump RHS, MG-BiCGSTAB to 1e-8"
+    elif cfg == "c1":
         p = W.sphere_case(32)
-        p.tol = 1e-8
-        p.mixed = True
-        return p, "sphere 32^3 uniform, manufactured RHS, mixed MG-BiCGSTAB to 1e-8"
-    raise SystemExit("unknown config " + cfg)
+        desc = "sphere 32^3 uniform, manufactured RHS, MG-BiCGSTAB to 1e-8"
+    else:
+        raise SystemExit("unknown config " + cfg)
+    p.tol = 1e-8
+    return p, desc
+
+
+def oracle_sample(cfg):
+    """Stored sample of the FP64 oracle's gauged solution of the workload
+    (tests/golden, written by a script that runs only the oracle), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "c3_membrane512_oracle_sample.npz")
+    if cfg != "c3" or not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def sampled_error(x, G):
+    """Relative L2 error of a gauged solution (device tensor, N + n_mghost)
+    against the oracle's on the stored sample of cells and membrane ghost
+    unknowns."""
+    import torch
+    N = x.numel() - int(G["n_mghost"])
+    idx = np.concatenate([G["cells"], N + G["mghost"]])
+    ref = np.concatenate([G["cell_values"], G["mghost_values"]])
+    got = x[torch.from_numpy(idx).to(x.device)].cpu().numpy()
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def time_solves(sol, f, reps):
+    """Wall milliseconds per solve over reps back-to-back solves (device
+    synchronised on both sides), the last solution and its stats."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x, st = sol.solve(f)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3, x, st
+
+
+def sweep_roofline(P, sol, f, T, N, traffic):
+    """Roofline of the level-0 red/black half-sweep (k0_sweep): its launches
+    in one solve timed with HIP events on the solve stream.  Algorithmic bytes
+    per launch: the other colour's values (T bytes each), this colour's RHS
+    and flag byte and its new values, over N/2 cells each: (1.5 T + 0.5) N."""
+    sol.kernel_timing(P.KERNEL_SWEEP0)
+    sol.solve(f)
+    tot, cnt = sol.kernel_timing(-1)
+    if not cnt:
+        return None
+    avg_ms = tot / cnt
+    bytes_launch = (1.5 * T + 0.5) * N
+    ach = bytes_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": (int(traffic) if traffic else None),
+            "kernel": "k0_sweep<%s>" % ("double" if T == 8 else "float"), "avg_launch_ms": round(avg_ms, 4),
+            "launches_per_solve": cnt, "algorithmic_bytes_per_launch": int(bytes_launch)}
+
+
+def hbm_ceiling(P, nbytes=4 << 30, reps=10):
+    """Streaming bandwidth of the device over buffers of nbytes each (far
+    above the 256 MB Infinity Cache), 16-byte accesses."""
+    out = {"buffer_bytes": nbytes}
+    for name, kind in (("copy", P.STREAM_COPY), ("read3_write1", P.STREAM_TRIAD), ("read", P.STREAM_READ)):
+        gbs, ms, moved = P.hbm_stream(kind, nbytes, reps)
+        out[name] = {"GB_s": round(gbs, 1), "ms": round(ms, 4), "bytes_per_pass": int(moved),
+                     "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        log("stream %s: %.1f GB/s (%.3f ms per pass of %d bytes)" % (name, gbs, ms, moved))
+    return out
 
 
 def sweep_source_digest():
@@ -97,11 +166,12 @@ def measured_solve_traffic(workload_key):
         return None
 
 
-def measured_traffic(workload_key):
-    """HBM bytes per launch of k0_sweep from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
-    the summary is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "k0_sweep_%s_traffic.md" % workload_key)
+def measured_traffic(workload_key, prec="f64"):
+    """HBM bytes per launch of k0_sweep in one precision ("f64" or "f32")
+    from the committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy), or None when the summary is missing or was taken
+    on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "k0_sweep_%s_%s_traffic.md" % (prec, workload_key))
     if not os.path.exists(path):
         return None
     vals = {}
@@ -171,15 +241,33 @@ def serving_bench(P, rates, nreq, seed=5, slots=16, budget=64 << 30):
         setup = np.array([d[6] for d in done])
         solve = np.array([d[7] for d in done])
         rest = lat - queue - setup - solve
+        # device occupancy: a request holds the device from admission to
+        # completion; the share of the span with at least one admitted
+        # request, and the mean number admitted at once
+        iv = sorted((d[5], d[1]) for d in done)
+        busy, cur0, cur1 = 0.0, None, None
+        for a0, a1 in iv:
+            if cur1 is None or a0 > cur1:
+                if cur1 is not None:
+                    busy += cur1 - cur0
+                cur0, cur1 = a0, a1
+            else:
+                cur1 = max(cur1, a1)
+        if cur1 is not None:
+            busy += cur1 - cur0
+        span_ms = span_s * 1e3
         out.append({"rate_req_s": rate, "requests": nreq, "ok": ok, "p50_ms": round(float(np.percentile(lat, 50)), 2),
                     "p99_ms": round(float(np.percentile(lat, 99)), 2), "solves_s": round(nreq / span_s, 2),
                     "Mpts_s": round(pts / span_s / 1e6, 1), "cache_hits": int(sum(d[8] for d in done)),
                     "mean_ms": {"queue": round(float(queue.mean()), 2), "setup": round(float(setup.mean()), 2),
-                                "solve": round(float(solve.mean()), 2), "release": round(float(rest.mean()), 2)}})
+                                "solve": round(float(solve.mean()), 2), "release": round(float(rest.mean()), 2)},
+                    "busy_frac": round(busy / span_ms, 3),
+                    "mean_active": round(float(sum(d[1] - d[5] for d in done)) / span_ms, 2),
+                    "mean_Mpts_per_request": round(pts / nreq / 1e6, 2)})
         log("serve rate %g req/s: p50 %.1f ms p99 %.1f ms, %.1f solves/s, %.0f Mpts/s, %d/%d ok; mean queue %.1f "
-            "set-up %.1f solve %.1f release %.1f ms" %
+            "set-up %.1f solve %.1f release %.1f ms; busy %.2f, %.2f active" %
             (rate, out[-1]["p50_ms"], out[-1]["p99_ms"], out[-1]["solves_s"], out[-1]["Mpts_s"], ok, nreq,
-             queue.mean(), setup.mean(), solve.mean(), rest.mean()))
+             queue.mean(), setup.mean(), solve.mean(), rest.mean(), out[-1]["busy_frac"], out[-1]["mean_active"]))
     srv.close()
     return {"workload": "Poisson arrivals, edge log-uniform [64, 384], cube or 2:1:1, 1-4 bodies (spheres, "
                         "ellipsoids, plates), noise RHS, mixed MG-BiCGSTAB to 1e-8; distinct requests per rate",
@@ -291,30 +379,52 @@ def ad_bench(P, n=512, components=3):
             "ok": sum(1 for r in rows if r[3] == 0 and r[4] <= 1e-10), "components": components}
 
 
-def cpu_baseline(cfg, budget_s):
-    """The FP64 oracle on a bounded sample of the same workload recipe."""
+def host_cpu():
+    """Model name and logical CPU count of the host."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(cfg, p, G, iters=2):
+    """The FP64 oracle on the benchmarked system itself, bounded: its set-up
+    (classification and ghost rows) and `iters` MG-BiCGSTAB iterations are
+    timed, and the solve time to 1e-8 is the time per iteration times the
+    oracle's own iteration count to 1e-8 (from the residual history of its
+    full solve, stored with the oracle sample).  Without that history (no
+    sample for this workload) the whole solve to 1e-8 is run."""
     import oracle
-    from paper_2605_04335_amd import workloads as W
-    n = {"c3": 256, "c2": 128, "c4": 256, "c1": 32}[cfg]
-    if cfg == "c3":
-        p = W.membrane_case(n)
-    elif cfg == "c2":
-        p = W.sphere_ellipsoid_case(n)
-    elif cfg == "c4":
-        p = W.spheres_case(n)
-    else:
-        p = W.sphere_case(n)
     t0 = time.time()
     S = oracle.setup(p.xf, p.yf, p.zf, p.bodies)
     t_setup = time.time() - t0
     b = oracle.assemble_rhs(S.xf, S.yf, S.zf, S.flags, S.st, p.f)
-    t0 = time.time()
-    x, info = oracle.solve(S.xf, S.yf, S.zf, S.flags, S.st, b, tol=1e-8, maxit=200)
-    t = time.time() - t0
+    model, ncpu = host_cpu()
     N = p.npts
-    return {"value": N / t / 1e6, "unit": "Mpts/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "same recipe at %d^3 (%d points): FP64 oracle MG-BiCGSTAB to 1e-8, %d iterations, %.1f s solve"
-                      " (+%.1f s setup)" % (n, N, info.iters, t, t_setup)}
+    if G is not None and "hist" in G:
+        its = int(np.argmax(G["hist"] <= 1e-8)) + 1
+        t0 = time.time()
+        x, info = oracle.solve(S.xf, S.yf, S.zf, S.flags, S.st, b, tol=1e-30, maxit=iters)
+        per = (time.time() - t0) / iters
+        t = per * its
+        sample = ("the %s system itself (%d points): oracle set-up %.1f s, then %d FP64 MG-BiCGSTAB iterations "
+                  "timed (%.2f s each) and scaled to the oracle's %d iterations to 1e-8" %
+                  (cfg, N, t_setup, iters, per, its))
+    else:
+        t0 = time.time()
+        x, info = oracle.solve(S.xf, S.yf, S.zf, S.flags, S.st, b, tol=1e-8, maxit=200)
+        t = time.time() - t0
+        its = info.iters
+        sample = "the %s system itself (%d points): FP64 oracle MG-BiCGSTAB to 1e-8, %d iterations, %.1f s solve " \
+                 "(+%.1f s set-up)" % (cfg, N, its, t, t_setup)
+    return {"value": round(N / t / 1e6, 3), "unit": "Mpts/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": sample, "host_cpu": model, "nproc": ncpu, "seconds_per_solve": round(t, 2),
+            "setup_s": round(t_setup, 2)}
 
 
 def main():
@@ -324,17 +434,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solve")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve and the accuracy ladder")
+    ap.add_argument("--no-ladder", action="store_true", help="skip the equal-accuracy tolerance ladder")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 1024^3 twenty-sphere leg")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streaming-bandwidth ceiling")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-moving", action="store_true", help="skip the moving-body time-step measurement")
     ap.add_argument("--no-ad", action="store_true", help="skip the advection-diffusion step measurement")
-    ap.add_argument("--serve-rates", default="5,20,80,200", help="request arrival rates (req/s) of the serving sweep")
-    ap.add_argument("--serve-requests", type=int, default=48, help="requests per arrival rate")
+    ap.add_argument("--serve-rates", default="5,10,20,50,100,200",
+                    help="request arrival rates (req/s) of the serving sweep")
+    ap.add_argument("--serve-requests", type=int, default=150, help="requests per arrival rate")
     ap.add_argument("--serve-slots", type=int, default=16, help="concurrently active solves in the server")
     ap.add_argument("--serve-small-budget-gb", type=int, default=8,
                     help="HBM budget (GB) of a second run at the highest rate, where admission binds; 0: skip")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="finish with 3 plain device copies of 1 GiB (reference for HBM byte counters)")
+                    help="finish with three plain 1 GiB stream copies (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PPE solve runs on a single MI355X; "
@@ -350,104 +464,148 @@ def main():
     p, desc = make_problem(args.config)
     nx, ny, nz = p.shape
     N = p.npts
+    key = KEYS[args.config]
+    G = oracle_sample(args.config)
     log("workload", desc)
     t0 = time.time()
     flags, cst = P.classify(p.xf, p.yf, p.zf, p.bodies)
     st = P.build_ghost_stencils(p.xf, p.yf, p.zf, p.bodies, flags)
     ng, nm, nfb = st.info()
-    solm = P.Solver(p.xf, p.yf, p.zf, flags, st, precision=P.PREC_MIXED, tol=p.tol, max_iter=60)
+    sol = P.Solver(p.xf, p.yf, p.zf, flags, st, precision=P.PREC_FP64, tol=p.tol, max_iter=200)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     log("setup %.2f s: ghosts %d, membrane ghosts %d, fallback %d" % (setup_s, ng, nm, nfb))
     f = torch.from_numpy(p.f).to(dev)
 
+    # ---- headline: the FP64 solve
     for _ in range(args.warmup):
-        x, stm = solm.solve(f)
-        log("warmup mixed: its %d outer %d rel %.2e %.1f ms" % (stm.iterations, stm.outer_steps, stm.rel_residual,
-                                                                stm.solve_ms))
+        x, s64 = sol.solve(f)
+        log("warmup fp64: its %d rel %.2e %.1f ms" % (s64.iterations, s64.rel_residual, s64.solve_ms))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dev_ms = []
     for k in range(args.steps):
-        x, stm = solm.solve(f)
-        dev_ms.append(stm.solve_ms)
-        log("step %d: its %d outer %d rel %.2e %.1f ms" % (k, stm.iterations, stm.outer_steps, stm.rel_residual,
-                                                           stm.solve_ms))
+        x, s64 = sol.solve(f)
+        dev_ms.append(s64.solve_ms)
+        log("step %d: its %d rel %.2e %.1f ms" % (k, s64.iterations, s64.rel_residual, s64.solve_ms))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall / args.steps * 1e3
     value = N / (ms_per_step / 1e3) / 1e6
-
-    # dominant kernel, timed per launch with HIP events on the library's stream
-    roof = None
-    kern_ms = {}
-    for kid, name in ((0, "k0_sweep"), (1, "k0_apply"), (2, "k_xr_update")):
-        P.lib().poisson_kernel_timing(solm.h, kid, 1, None, None)
-        solm.solve(f)
-        tot = P.ctypes.c_double()
-        cnt = P.ctypes.c_int64()
-        P.lib().poisson_kernel_timing(solm.h, -1, 1, P.ctypes.byref(tot), P.ctypes.byref(cnt))
-        kern_ms[name] = (tot.value, cnt.value)
-    tot, cnt = kern_ms["k0_sweep"]
-    if cnt:
-        avg_ms = tot / cnt
-        T = 4  # FP32 inner vectors
-        # red/black half-sweep over half of the cells: read the other colour's values, this colour's RHS and
-        # flag byte, write this colour's values
-        bytes_launch = (1.5 * T + 0.5) * N
-        ach = bytes_launch / (avg_ms * 1e-3) / 1e9
-        tr = measured_traffic({"c3": "membrane512", "c2": "spheroids256", "c4": "spheres1024",
-                               "c1": "sphere32"}[args.config])
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": (int(tr) if tr else None), "kernel": "k0_sweep<float>",
-                "avg_launch_ms": round(avg_ms, 4), "launches_per_solve": cnt,
-                "algorithmic_bytes_per_launch": int(bytes_launch)}
-
+    err64 = sampled_error(x, G) if G is not None else None
+    roof = sweep_roofline(P, sol, f, 8, N, measured_traffic(key, "f64"))
     out = {"metric": METRIC, "value": round(value, 2), "unit": "Mpts/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32+bf16", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": desc, "grid": [nx, ny, nz], "points": N, "tol": p.tol,
-                      "precision": "mixed (FP32/BF16 V-cycle and inner BiCGSTAB, FP64 refinement)",
-                      "iterations": stm.iterations, "outer_steps": stm.outer_steps,
-                      "rel_residual": stm.rel_residual, "device_ms_per_solve": round(float(np.median(dev_ms)), 3),
-                      "setup_s": round(setup_s, 2), "ghosts": ng, "membrane_ghosts": nm, "fallback_rows": nfb},
-           "roofline": roof,
-           "kernel_ms": {k: {"total_ms": round(v[0], 3), "launches": v[1]} for k, v in kern_ms.items()}}
-    # whole solve: measured HBM bytes of every solve kernel over the solve time
-    ts = measured_solve_traffic({"c3": "membrane512", "c2": "spheroids256", "c4": "spheres1024",
-                                 "c1": "sphere32"}[args.config])
-    if ts:
-        gbs = ts / (ms_per_step * 1e-3) / 1e9
-        out["solve_hbm"] = {"bytes_per_solve": int(ts), "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    # whole solve against the compulsory-traffic model of the mixed form: per
-    # inner iteration 86 B/pt of FP32 Krylov kernels and two FP32/BF16
-    # V-cycles of 75 B/pt; per refinement step an FP64 residual and update of
-    # 41 B/pt
-    model = (236.0 * stm.iterations + 41.0 * stm.outer_steps) * N
-    gbm = model / (ms_per_step * 1e-3) / 1e9
-    out["solve_model"] = {"bytes_per_solve": int(model), "achieved": round(gbm, 1), "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": round(gbm / HBM_PEAK_GBS, 4)}
+                      "precision": "FP64 throughout (vectors, V-cycle, dots, ghost weights)",
+                      "iterations": s64.iterations, "rel_residual": s64.rel_residual,
+                      "device_ms_per_solve": round(float(np.median(dev_ms)), 3), "setup_s": round(setup_s, 2),
+                      "ghosts": ng, "membrane_ghosts": nm, "fallback_rows": nfb,
+                      "rel_error_vs_oracle_sample": err64},
+           "roofline": roof}
+    # whole FP64 solve against the compulsory-traffic model (463 B/pt/iteration)
+    model = 463.0 * s64.iterations * N
+    out["solve_model"] = {"bytes_per_solve": int(model), "GB_s": round(model / (ms_per_step * 1e-3) / 1e9, 1),
+                          "frac": round(model / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if roof:
+        log("fp64 %.1f ms/solve (%.1f Mpts/s, %d its); k0_sweep<double> %.1f GB/s (%.3f of peak); error vs oracle "
+            "sample %s" % (ms_per_step, value, s64.iterations, roof["achieved"], roof["frac"], err64))
+    x = None
 
-    if not args.no_fp64:
+    # ---- the mixed form on the same system
+    if not args.no_mixed:
+        solm = P.Solver(p.xf, p.yf, p.zf, flags, st, precision=P.PREC_MIXED, tol=p.tol, max_iter=60)
+        solm.solve(f)
+        reps = max(2, min(5, args.steps))
+        msm, xm, sm = time_solves(solm, f, reps)
+        errm = sampled_error(xm, G) if G is not None else None
+        roofm = sweep_roofline(P, solm, f, 4, N, measured_traffic(key, "f32"))
+        ts = measured_solve_traffic(key)
+        out["mixed"] = {"ms_per_solve": round(msm, 3), "Mpts_s": round(N / msm * 1e3 / 1e6, 2),
+                        "dtype": "f64+f32+bf16", "tol": p.tol, "iterations": sm.iterations,
+                        "outer_steps": sm.outer_steps, "rel_residual": sm.rel_residual,
+                        "speedup_vs_fp64": round(ms_per_step / msm, 3), "rel_error_vs_oracle_sample": errm,
+                        "roofline": roofm}
+        if ts:
+            out["mixed"]["solve_hbm"] = {"bytes_per_solve": int(ts), "GB_s": round(ts / (msm * 1e-3) / 1e9, 1),
+                                         "frac": round(ts / (msm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log("mixed %.1f ms/solve (%d its, %d outer): %.2fx; error vs oracle sample %s" %
+            (msm, sm.iterations, sm.outer_steps, ms_per_step / msm, errm))
+        xm = None
         del solm
         torch.cuda.empty_cache()
-        sol64 = P.Solver(p.xf, p.yf, p.zf, flags, st, precision=P.PREC_FP64, tol=p.tol, max_iter=100)
-        x64, s64 = sol64.solve(f)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = max(1, min(3, args.steps))
-        for _ in range(reps):
-            x64, s64 = sol64.solve(f)
-        torch.cuda.synchronize()
-        ms64 = (time.perf_counter() - t0) / reps * 1e3
-        err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
-        out["config"]["fp64"] = {"ms_per_solve": round(ms64, 3), "Mpts_s": round(N / ms64 * 1e3 / 1e6, 2),
-                                 "iterations": s64.iterations, "rel_residual": s64.rel_residual}
-        out["config"]["mixed_speedup_vs_fp64"] = round(ms64 / ms_per_step, 3)
-        out["config"]["mixed_rel_error_vs_fp64"] = err
-        log("fp64: %.1f ms/solve, %d its; mixed speed-up %.2fx, rel error %.2e" % (ms64, s64.iterations,
-                                                                                   ms64 / ms_per_step, err))
+        # equal accuracy: for each form the loosest tolerance whose solution is
+        # within 1e-8 of the oracle's (on the stored sample), and the times there
+        if G is not None and not args.no_ladder:
+            ladder = [1e-8, 5e-9, 2e-9, 1e-9, 5e-10, 2e-10, 1e-10]
+            eq = {}
+            for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+                rows = []
+                for tol in ladder:
+                    sl = P.Solver(p.xf, p.yf, p.zf, flags, st, precision=prec, tol=tol, max_iter=200)
+                    sl.solve(f)
+                    ms, xl, sx = time_solves(sl, f, 2)
+                    e = sampled_error(xl, G)
+                    rows.append({"tol": tol, "ms": round(ms, 3), "iterations": sx.iterations, "error": e})
+                    xl = None
+                    del sl
+                    log("ladder %s tol %.0e: %.1f ms, %d its, error %.2e" % (name, tol, ms, sx.iterations, e))
+                    if e <= 1e-8:
+                        break
+                torch.cuda.empty_cache()
+                eq[name] = rows
+            f64ok = [r for r in eq["fp64"] if r["error"] <= 1e-8]
+            mok = [r for r in eq["mixed"] if r["error"] <= 1e-8]
+            out["mixed"]["equal_accuracy"] = {
+                "target": "rel L2 error <= 1e-8 against the oracle sample", "fp64": eq["fp64"], "mixed": eq["mixed"],
+                "speedup": (round(f64ok[0]["ms"] / mok[0]["ms"], 3) if f64ok and mok else None)}
+    del sol
+    torch.cuda.empty_cache()
+
+    # ---- the 1024^3, twenty-sphere case in both forms
+    if not args.no_c4 and args.config != "c4":
+        from paper_2605_04335_amd import workloads as W
+        q = W.spheres_case(1024)
+        fl4, _ = P.classify(q.xf, q.yf, q.zf, q.bodies)
+        st4 = P.build_ghost_stencils(q.xf, q.yf, q.zf, q.bodies, fl4)
+        f4 = torch.from_numpy(q.f).to(dev)
+        leg = {"workload": "20 spheres 1024^3 uniform, Gaussian-bump RHS, MG-BiCGSTAB to 1e-8",
+               "points": q.npts, "ghosts": st4.info()[0]}
+        keep = None
+        for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+            s4 = P.Solver(q.xf, q.yf, q.zf, fl4, st4, precision=prec, tol=1e-8, max_iter=200)
+            s4.solve(f4)
+            ms, x4, t4 = time_solves(s4, f4, 2)
+            leg[name] = {"ms_per_solve": round(ms, 2), "Mpts_s": round(q.npts / ms * 1e3 / 1e6, 1),
+                         "iterations": t4.iterations, "outer_steps": t4.outer_steps,
+                         "rel_residual": t4.rel_residual}
+            if keep is None:
+                keep = x4
+            else:
+                d = x4 - keep
+                leg["mixed_rel_diff_vs_fp64"] = float(torch.linalg.norm(d) / torch.linalg.norm(keep))
+            x4 = None
+            del s4
+            torch.cuda.empty_cache()
+            log("c4 %s: %.1f ms/solve, %d its" % (name, ms, t4.iterations))
+        leg["speedup"] = round(leg["fp64"]["ms_per_solve"] / leg["mixed"]["ms_per_solve"], 3)
+        leg["oracle"] = "not run: the 1024^3 oracle solve needs ~90 GB of host memory and hours of CPU time"
+        out["c4"] = leg
+        keep = f4 = None
+        del st4, fl4
+        torch.cuda.empty_cache()
+
+    # ---- the device's streaming ceiling
+    if not args.no_stream:
+        ceil = hbm_ceiling(P)
+        out["hbm_ceiling"] = ceil
+        cgb = ceil["read3_write1"]["GB_s"]
+        for r in (out.get("roofline"), out.get("mixed", {}).get("roofline")):
+            if r:
+                r["ceiling_GB_s"] = cgb
+                r["frac_of_ceiling"] = round(r["achieved"] / cgb, 4)
+
     if not args.no_serve:
         out["serving"] = serving_bench(P, [float(r) for r in args.serve_rates.split(",")], args.serve_requests,
                                        slots=args.serve_slots)
@@ -462,19 +620,12 @@ def main():
     if not args.no_ad:
         out["advection_diffusion"] = ad_bench(P)
     if args.copy_calibration:
-        import torch as _t
-        nbytes = 1 << 30
-        src = _t.ones(nbytes, dtype=_t.uint8, device=dev)
-        dst = _t.empty_like(src)
-        _t.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        _t.cuda.synchronize()
-        log("copy calibration: 3 device-to-device copies of %d bytes" % nbytes)
-        del src, dst
+        P.hbm_stream(P.STREAM_COPY, 1 << 30, 3)
+        log("copy calibration: 3 stream copies of 1 GiB (k_st_copy)")
     if rank == 0 and not args.no_cpu:
         try:
-            out["cpu_baseline"] = cpu_baseline(args.config, 30)
+            out["cpu_baseline"] = cpu_baseline(args.config, p, G)
+            log("cpu baseline: %s Mpts/s (%s)" % (out["cpu_baseline"]["value"], out["cpu_baseline"]["sample"]))
         except Exception as e:  # reported, never fatal
             out["cpu_baseline"] = {"value": None, "error": repr(e)}
     print(json.dumps(out), flush=True)

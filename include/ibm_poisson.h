@@ -231,7 +231,9 @@ int32_t poisson_workspace_estimate(int32_t nx, int32_t ny, int32_t nz, int64_t n
                                    size_t *bytes);
 
 /*
- * poisson_solve -- the PPE solve: RHS assembly (fluid f projected to zero
+ * poisson_solve -- the PPE solve of the fractional step (Sec. 2.1: the
+ * pressure Poisson equation, solved by BiCGStab with a preconditioner; Sec.
+ * 2.5, module 3: matrix-free bulk rows plus ELLPACK ghost rows): RHS assembly (fluid f projected to zero
  * volume-weighted mean, pin row 0, ghost rows sG*dlb*g), right-preconditioned
  * BiCGSTAB (van der Vorst 1992) with a geometric-multigrid V-cycle on the
  * pinned system, FP64 (or mixed: FP32/BF16 inner solves inside FP64
@@ -376,6 +378,24 @@ int32_t poisson_solve_assembled(poisson_ctx *ctx, const double *b_dev, double *x
  * != 0 clears) the accumulated milliseconds and launch count, then selects
  * `kernel` for the following solves. */
 int32_t poisson_kernel_timing(poisson_ctx *ctx, int32_t kernel, int32_t reset, double *total_ms, int64_t *launches);
+
+/*
+ * ibm_hbm_stream -- the device's streaming bandwidth, the ceiling quoted
+ * beside the HBM peak for the solve's bandwidth-bound kernels.  Allocates the
+ * buffers (each `bytes` long, 1 MiB .. 64 GiB; use sizes far above the
+ * 256 MB Infinity Cache), fills them, runs one untimed pass and then `reps`
+ * (1..1000) timed passes of one stream on `stream`, bracketed by HIP events:
+ *   IBM_STREAM_COPY   b = a                    (1 read : 1 write)
+ *   IBM_STREAM_TRIAD  d = a + b + c, FP32      (3 reads : 1 write, the mix of a red/black half-sweep)
+ *   IBM_STREAM_READ   per-block sums of a      (read only)
+ * Every lane moves 16 bytes per access.  *ms gets the mean milliseconds per
+ * pass and *bytes_moved the bytes read plus written per pass.  Synchronises
+ * the stream before returning; the buffers are released.
+ */
+#define IBM_STREAM_COPY 0
+#define IBM_STREAM_TRIAD 1
+#define IBM_STREAM_READ 2
+int32_t ibm_hbm_stream(int32_t kind, size_t bytes, int32_t reps, double *ms, double *bytes_moved, void *stream);
 
 /* Multigrid level count and unknown counts of a context (any pointer may be NULL). */
 int32_t poisson_level_info(poisson_ctx *ctx, int32_t *levels, int64_t *n_unknowns, int64_t *n_ghost,

@@ -102,7 +102,7 @@ EXPORTS = ["ibm_classify", "ibm_build_ghost_stencils", "ibm_stencils_info", "ibm
            "poisson_submit", "poisson_poll", "poisson_server_drain", "poisson_server_destroy", "ibm_last_error",
            "poisson_update", "poisson_solve_from", "ibm_fill_fresh", "ibm_surface_forces",
            "ibm_build_ghost_stencils_bc", "ibm_ad_default_opts", "ibm_ad_setup", "ibm_ad_apply", "ibm_ad_solve",
-           "ibm_ad_destroy"]
+           "ibm_ad_destroy", "ibm_hbm_stream", "poisson_kernel_timing"]
 
 _lib = None
 
@@ -182,6 +182,22 @@ def default_opts(**kw) -> PoissonOpts:
             v = PRECOND_SRJ if v == "srj" else PRECOND_MG
         setattr(o, k, v)
     return o
+
+
+STREAM_COPY, STREAM_TRIAD, STREAM_READ = 0, 1, 2
+
+
+def hbm_stream(kind: int, nbytes: int, reps: int = 10):
+    """Streaming bandwidth of the device (ibm_hbm_stream): (GB/s, ms per
+    pass, bytes read plus written per pass)."""
+    ms = ctypes.c_double()
+    moved = ctypes.c_double()
+    _check(lib().ibm_hbm_stream(ctypes.c_int32(kind), ctypes.c_size_t(nbytes), ctypes.c_int32(reps),
+                                ctypes.byref(ms), ctypes.byref(moved), _stream()), "ibm_hbm_stream")
+    return moved.value / (ms.value * 1e-3) / 1e9, ms.value, moved.value
+
+
+KERNEL_SWEEP0, KERNEL_APPLY0, KERNEL_XR = 0, 1, 2
 
 
 # ------------------------------------------------------------------ geometry
@@ -341,6 +357,16 @@ class Solver:
     @property
     def n_unknowns(self):
         return self.N + self.nm
+
+    def kernel_timing(self, kernel: int, reset: bool = True):
+        """Select a kernel for per-launch HIP-event timing in the following
+        solves (-1: off); returns (total ms, launches) accumulated so far."""
+        tot = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib().poisson_kernel_timing(self.h, ctypes.c_int32(kernel), ctypes.c_int32(1 if reset else 0),
+                                           ctypes.byref(tot), ctypes.byref(cnt)), "poisson_kernel_timing")
+        return tot.value, cnt.value
+
 
     def _vec(self, device="cuda"):
         import torch

@@ -29,6 +29,7 @@ UNITS = {
     "server.hip": [],
     "forces.hip": ["-ffp-contract=off"],
     "ad.hip": ["-ffp-contract=off"],
+    "stream.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

@@ -315,10 +315,11 @@ extern "C" int32_t poisson_submit(poisson_server *S, const poisson_request *q, u
         }
         const poisson_opts &po = r->opts;  // field by field: no padding bytes in the key
         const double od[2] = {po.tol, po.inner_tol};
-        const int32_t oi[7] = {po.precision, po.max_iter, po.nu1, po.nu2, po.coarse_sweeps, po.max_outer,
-                               po.use_graph};
+        const int32_t oi[9] = {po.precision, po.max_iter,    po.nu1,     po.nu2,       po.coarse_sweeps,
+                               po.max_outer, po.use_graph, po.precond, po.srj_sweeps};
+        static_assert(sizeof(poisson_opts) == 56, "poisson_opts changed: every field belongs in the cache key");
         append_bytes(r->key, od, 2);
-        append_bytes(r->key, oi, 7);
+        append_bytes(r->key, oi, 9);
         // footprint: solver workspace plus classification temporaries, with a
         // generous bound on the ghost rows (one cell in eight)
         r->footprint = estimate_bytes(r->g.n[0], r->g.n[1], r->g.n[2], N / 8, q->opts.precision) + (size_t)N +

@@ -161,9 +161,11 @@ def test_fp64_solve_matches_oracle(torch_cuda, name):
     x = x.cpu().numpy()
     assert stats.status == 0 and stats.rel_residual <= 1e-12
     assert rel(x, xo) < 1e-10
-    # the oracle's own residual of the GPU solution
-    xr = x.copy()
-    r = oracle.apply(p.xf, p.yf, p.zf, O.flags, O.st, xr)
+    # the oracle's own residual of the GPU solution: the gauge adds a constant,
+    # which every row but the pin's maps to zero, so the pin row is left out
+    r = bo - oracle.apply(p.xf, p.yf, p.zf, O.flags, O.st, x)
+    r[int(np.nonzero(O.flags & 8)[0][0])] = 0.0
+    assert np.linalg.norm(r) <= 2e-12 * np.linalg.norm(bo)
     assert stats.iterations <= info.iters + 3
 
 
@@ -175,8 +177,9 @@ def test_fp64_solve_config_tolerance_c1(torch_cuda):
     xo, bo, _, info = oracle.solve_problem(O, p.f, tol=1e-13)
     flags, st, sol, _ = gpu_setup(torch, p, tol=1e-10)
     x, stats = sol.solve(torch.from_numpy(p.f).cuda())
-    assert stats.status == 0
-    assert rel(x.cpu().numpy(), xo) < 1e-9
+    assert stats.status == 0 and stats.rel_residual <= 1e-10
+    # the oracle itself at this tolerance is 3.4e-11 from its 1e-13 solution
+    assert rel(x.cpu().numpy(), xo) < 1e-10
 
 
 @pytest.mark.parametrize("name", ["c1", "c2_64", "membrane_64", "mixed_bodies_48"])

@@ -186,6 +186,42 @@ def test_setup_cache(P):
         srv.close()
 
 
+def _poll_done(P, srv, t, timeout_s=120):
+    t0 = time.time()
+    while True:
+        rc, state, x, st, tm = srv.poll(t)
+        if rc != P.IBM_EAGAIN:
+            return rc, x, st, tm
+        assert time.time() - t0 < timeout_s, "serving timed out"
+        time.sleep(0.002)
+
+
+def test_cache_key_holds_every_option(P):
+    """Requests that differ only in the preconditioner, or only in the SRJ
+    sweep count, get set-ups of their own: no cache hit, and each result and
+    iteration count equals a solo solve with the same options."""
+    (a,) = requests(1, 16, 40, 48)
+    variants = [dict(precision="fp64", tol=1e-8, precond="mg"),
+                dict(precision="fp64", tol=1e-8, precond="srj", srj_sweeps=8),
+                dict(precision="fp64", tol=1e-8, precond="srj", srj_sweeps=12),
+                dict(precision="fp64", tol=1e-8, precond="mg")]
+    srv = P.Server(hbm_budget=16 << 30, max_slots=1, cache_entries=8)
+    try:
+        got = []
+        for v in variants:
+            rc, x, st, tm = _poll_done(P, srv, srv.submit(a.xf, a.yf, a.zf, a.bodies, a.f, max_iter=1000, **v))
+            assert rc == P.IBM_OK
+            got.append((x, st.iterations, tm.cache_hit))
+    finally:
+        srv.close()
+    say("iterations", [g[1] for g in got], "cache hits", [g[2] for g in got])
+    assert [g[2] for g in got] == [0, 0, 0, 1]
+    for v, (x, its, _) in zip(variants, got):
+        xa, sa = solve_alone(P, a, max_iter=1000, **v)
+        assert its == sa.iterations
+        assert np.array_equal(x, xa)
+
+
 def test_burst_with_cache_all_succeed(P):
     """Requests arriving together, with new set-ups (and their first graph
     captures) overlapping cached ones and evictions: every one succeeds.
