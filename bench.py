@@ -146,11 +146,12 @@ def solver_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_solve_traffic(workload_key):
-    """HBM bytes of one whole mixed solve (FETCH_SIZE + WRITE_SIZE of every
-    solve kernel, scaled by a plain copy) from the committed rocprofv3
-    summary, or None when missing or taken on other sources."""
-    path = os.path.join(ROOT, "profiles", "mg_bicgstab_%s_solve_traffic.md" % workload_key)
+def measured_solve_traffic(workload_key, prec="f64"):
+    """HBM bytes of one whole solve in one form ("f64" or "mixed"):
+    FETCH_SIZE + WRITE_SIZE of every solve kernel, scaled by a plain copy,
+    from the committed rocprofv3 summary, or None when missing or taken on
+    other sources."""
+    path = os.path.join(ROOT, "profiles", "mg_bicgstab_%s_%s_solve_traffic.md" % (prec, workload_key))
     if not os.path.exists(path):
         return None
     vals = {}
@@ -508,6 +509,12 @@ def main():
     model = 463.0 * s64.iterations * N
     out["solve_model"] = {"bytes_per_solve": int(model), "GB_s": round(model / (ms_per_step * 1e-3) / 1e9, 1),
                           "frac": round(model / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    # and its measured HBM traffic (every solve kernel's counters)
+    ts64 = measured_solve_traffic(key, "f64")
+    if ts64:
+        out["solve_hbm"] = {"bytes_per_solve": int(ts64), "GB_s": round(ts64 / (ms_per_step * 1e-3) / 1e9, 1),
+                            "frac": round(ts64 / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "vs_model": round(ts64 / model, 3)}
     if roof:
         log("fp64 %.1f ms/solve (%.1f Mpts/s, %d its); k0_sweep<double> %.1f GB/s (%.3f of peak); error vs oracle "
             "sample %s" % (ms_per_step, value, s64.iterations, roof["achieved"], roof["frac"], err64))
@@ -521,7 +528,7 @@ def main():
         msm, xm, sm = time_solves(solm, f, reps)
         errm = sampled_error(xm, G) if G is not None else None
         roofm = sweep_roofline(P, solm, f, 4, N, measured_traffic(key, "f32"))
-        ts = measured_solve_traffic(key)
+        ts = measured_solve_traffic(key, "mixed")
         out["mixed"] = {"ms_per_solve": round(msm, 3), "Mpts_s": round(N / msm * 1e3 / 1e6, 2),
                         "dtype": "f64+f32+bf16", "tol": p.tol, "iterations": sm.iterations,
                         "outer_steps": sm.outer_steps, "rel_residual": sm.rel_residual,

@@ -507,85 +507,91 @@ __global__ void __launch_bounds__(TPB) k_csweep(Lv L, Geo G, T *__restrict__ x, 
 // Level-0 Gauss-Seidel half-sweep of colour c (ordinary mode): xc, bc, fc
 // are this colour's arrays, xo the other colour's.  The other colour's slot
 // at the same (h, j, k) is an x neighbour of the cell in plane k and its z
-// neighbour in planes k-1 and k+1, so on FP64 levels each thread walks its
-// planes with a three-plane window of those values in registers; four
-// planes per step, all loads issued before any store.  pin_s: the pin's slot within this
-// colour (or -1), whose RHS carries the sink.
-constexpr int U0 = 4;
+// neighbour in planes k-1 and k+1, so each thread walks its planes with a
+// three-plane window of those values in registers.  SWP planes per step
+// (two in FP64, four in FP32), every load of a step issued before any
+// arithmetic and none of them conditional: the plane above is read from a
+// clamped index (its coefficient is zero at the top wall) and the z
+// coefficients are loaded with the values.  Addresses are 32-bit offsets
+// from block-uniform bases at the tile's first plane (the tile spans at most
+// kz + 1 planes; plane_span_ok() holds for every level-0 geometry).  The new
+// values are written with non-temporal stores: the next kernel to read them
+// is a later half-sweep, long after a level-0 vector has left the caches.
+// pin_s: the pin's slot within this colour (or -1), whose RHS carries the sink.
+template <class T>
+struct SweepPlanes {
+    static constexpr int n = 2;
+};
+template <>
+struct SweepPlanes<float> {
+    static constexpr int n = 4;
+};
+
+template <class T>
+__device__ __forceinline__ void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
+
+// byte offsets of a tile's planes fit in 32 bits
+inline bool plane_span_ok(long long plane_slots, int kz, size_t elem) { return plane_slots * (kz + 2) * (long long)elem < (1LL << 32); }
+
 template <class T>
 __global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T *__restrict__ xc,
                                                 const T *__restrict__ xo, const T *__restrict__ bc,
                                                 const uint8_t *__restrict__ fc, const double *__restrict__ sink, int c)
 {
+    constexpr int UP = SweepPlanes<T>::n;
     int h, j, k0, k1;
     if (!geo_tile(G, h, j, k0, k1)) return;
     const Col0 q = col0(L, c, h, j);
-    const long long pl = (long long)L.H * L.ny;
-    const long long col = h + (long long)L.H * j;
-    if constexpr (!std::is_same<T, double>::value) {
-        // FP32 levels: every neighbour loaded per plane measured faster here
-        for (int kb = k0; kb < k1; kb += U0) {
-            double nb[U0], bb[U0], dg[U0];
-            uint8_t fl[U0];
-#pragma unroll
-            for (int u = 0; u < U0; ++u) {
-                const int k = min(kb + u, k1 - 1);
-                const long long s = col + pl * k;
-                fl[u] = fc[s];
-                bb[u] = ld(bc, s);
-                nb[u] = col0_sum(L, q, xo, s, k, pl, dg[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < U0; ++u) {
-                const long long s = col + pl * (kb + u);
-                if (kb + u >= k1 || (fl[u] & (F_SOLID | F_MGHOST))) continue;
-                double b0 = bb[u];
-                if (s == pin_s) b0 -= sink[0];
-                st(xc, s, (nb[u] - b0) / dg[u]);
-            }
-        }
-        return;
-    }
+    const uint32_t pl = (uint32_t)(L.H * L.ny);
+    const int kb = max(k0 - 1, 0);
+    const T *xb = xo + (long long)pl * kb;
+    const T *bp = bc + (long long)pl * kb;
+    const uint8_t *fb = fc + (long long)pl * kb;
+    T *xw = xc + (long long)pl * kb;
+    const uint32_t col = (uint32_t)(h + L.H * j);
+    const int ox0 = q.oxp[0] + q.oxm[0], ox1 = q.oxp[1] + q.oxm[1];  // the x neighbour that is not the centre
+    const int oyp = (int)q.oyp, oym = (int)q.oym;
+    const long long pin_rel = pin_s >= 0 ? pin_s - (long long)pl * kb : -1;
     // centres of planes k-1 and k (zero coefficient outside the grid)
-    double cprev = k0 > 0 ? ld(xo, col + pl * (k0 - 1)) : 0.0;
-    double ccur = ld(xo, col + pl * k0);
-    for (int kb = k0; kb < k1; kb += U0) {
-        double cn[U0], xs[U0], yp[U0], ym[U0], bb[U0];
-        uint8_t fl[U0];
+    double cprev = k0 > 0 ? (double)ldu(xb, col + pl * (uint32_t)(k0 - 1 - kb)) : 0.0;
+    double ccur = ldu(xb, col + pl * (uint32_t)(k0 - kb));
+    for (int ks = k0; ks < k1; ks += UP) {
+        double cn[UP], xs[UP], yp[UP], ym[UP], bb[UP], czp[UP], czm[UP];
+        uint8_t fl[UP];
 #pragma unroll
-        for (int u = 0; u < U0; ++u) {
-            const int k = min(kb + u, k1 - 1);
-            const long long s = col + pl * k;
+        for (int u = 0; u < UP; ++u) {
+            const int k = min(ks + u, k1 - 1);
+            const uint32_t s = col + pl * (uint32_t)(k - kb);
             const bool t = k & 1;
-            const int o = t ? q.oxp[1] + q.oxm[1] : q.oxp[0] + q.oxm[0];  // the x neighbour that is not the centre
-            cn[u] = k + 1 < L.nz ? ld(xo, s + pl) : 0.0;                   // centre of plane k+1
-            xs[u] = ld(xo, s + o);
-            yp[u] = ld(xo, s + q.oyp);
-            ym[u] = ld(xo, s + q.oym);
-            fl[u] = fc[s];
-            bb[u] = ld(bc, s);
+            cn[u] = ldu(xb, col + pl * (uint32_t)(min(k + 1, L.nz - 1) - kb));  // centre of plane k+1
+            xs[u] = ldu(xb, s + (uint32_t)(t ? ox1 : ox0));
+            yp[u] = ldu(xb, s + (uint32_t)oyp);
+            ym[u] = ldu(xb, s + (uint32_t)oym);
+            fl[u] = ldu(fb, s);
+            bb[u] = ldu(bp, s);
+            czp[u] = L.cp[2][k];  // zero at the walls
+            czm[u] = L.cm[2][k];
         }
 #pragma unroll
-        for (int u = 0; u < U0; ++u) {
-            const int k = kb + u;
+        for (int u = 0; u < UP; ++u) {
+            const int k = ks + u;
             const double cc = u == 0 ? ccur : cn[u - 1];
             const double cm = u == 0 ? cprev : (u == 1 ? ccur : cn[u - 2]);
             if (k >= k1) continue;
-            const long long s = col + pl * k;
+            const uint32_t s = col + pl * (uint32_t)(k - kb);
             const bool t = k & 1;
             const double cpx = t ? q.cpx[1] : q.cpx[0], cmx = t ? q.cmx[1] : q.cmx[0];
             const int oxp = t ? q.oxp[1] : q.oxp[0], oxm = t ? q.oxm[1] : q.oxm[0];
             const double xpv = oxp == 0 ? cc : xs[u], xmv = oxm == 0 ? cc : xs[u];
-            const double czp = L.cp[2][k], czm = L.cm[2][k];  // zero at the walls
-            const double dg = cpx + cmx + q.cpy + q.cmy + czp + czm;
-            const double nb = cpx * xpv + cmx * xmv + q.cpy * yp[u] + q.cmy * ym[u] + czp * cn[u] + czm * cm;
+            const double dg = cpx + cmx + q.cpy + q.cmy + czp[u] + czm[u];
+            const double nb = cpx * xpv + cmx * xmv + q.cpy * yp[u] + q.cmy * ym[u] + czp[u] * cn[u] + czm[u] * cm;
             if (fl[u] & (F_SOLID | F_MGHOST)) continue;
             double b0 = bb[u];
-            if (s == pin_s) b0 -= sink[0];
-            st(xc, s, (nb - b0) / dg);
+            if ((long long)s == pin_rel) b0 -= sink[0];
+            st_nt(xw + s, (T)((nb - b0) / dg));
         }
-        cprev = cn[U0 - 2];
-        ccur = cn[U0 - 1];
+        cprev = cn[UP - 2];
+        ccur = cn[UP - 1];
     }
 }
 

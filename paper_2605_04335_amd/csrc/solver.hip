@@ -871,8 +871,11 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
             }
         level_geometry(L, faces, s);
     }
-    // level 0: shorter plane runs per thread (more tiles) measured faster
+    // level 0: shorter plane runs per thread (more tiles) measured faster;
+    // the half-sweep addresses a tile's planes with 32-bit byte offsets
     c->lv[0].geo = make_geo(c->lv[0].H, c->lv[0].n[1], c->lv[0].n[2], 16384);
+    IBM_REQUIRE(plane_span_ok((long long)c->lv[0].H * c->lv[0].n[1], c->lv[0].geo.kz, sizeof(double)), IBM_EINVAL,
+                "grid planes too large for the level-0 sweep's 32-bit offsets");
     c->N2 = 2 * c->lv[0].Nh;
     // prolongation maps of each level from its coarse parent
     for (int l = 1; l < nl; ++l) {

@@ -33,17 +33,17 @@ def test_counter_summaries_follow_the_sources(monkeypatch):
     # sources with the digest the counters were taken on: the summaries' figures
     monkeypatch.setattr(bench, "sweep_source_digest", lambda: summary_digest("k0_sweep_f32_membrane512_traffic.md"))
     monkeypatch.setattr(bench, "solver_source_digest",
-                        lambda: summary_digest("mg_bicgstab_membrane512_solve_traffic.md"))
+                        lambda: summary_digest("mg_bicgstab_mixed_membrane512_solve_traffic.md"))
     assert bench.measured_traffic("membrane512", "f32") > 0.8 * (1.5 * 4 + 0.5) * 512 ** 3
-    assert bench.measured_solve_traffic("membrane512") > 1e11
+    assert bench.measured_solve_traffic("membrane512", "mixed") > 1e11
     # a workload without a summary has no measured traffic
     assert bench.measured_traffic("no_such_workload", "f32") is None
-    assert bench.measured_solve_traffic("no_such_workload") is None
+    assert bench.measured_solve_traffic("no_such_workload", "mixed") is None
     # sources edited since the counters were taken: no figures
     monkeypatch.setattr(bench, "sweep_source_digest", lambda: "0000000000000000")
     monkeypatch.setattr(bench, "solver_source_digest", lambda: "0000000000000000")
     assert bench.measured_traffic("membrane512", "f32") is None
-    assert bench.measured_solve_traffic("membrane512") is None
+    assert bench.measured_solve_traffic("membrane512", "mixed") is None
 
 
 def test_sweep_algorithmic_bytes_match_the_summary():

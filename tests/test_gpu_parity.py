@@ -5,6 +5,7 @@ Classification and ghost lists must match bit-exactly; stencil weights to
 to 1e-10 relative L2 against the oracle's reference solution (converged to
 its floor); mixed-precision solutions to 1e-8.
 """
+import math
 import sys
 
 import numpy as np
@@ -206,23 +207,48 @@ def test_solve_deterministic(torch_cuda):
 
 
 def test_manufactured_discrete_solution(torch_cuda):
-    """b = A x_true: the solver must return x_true within kappa * tol."""
+    """b = A x_true (the oracle's operator) on the 96^3 stretched sphere +
+    ellipsoid case: the GPU solve returns x_true within the error that its
+    residual allows.  The pinned system's spectrum spans lambda_max (power
+    iteration with the oracle's operator, ~1.75e5 here) down to ~0.026, the
+    near-constant mode the single-cell pin leaves: kappa ~ 6.7e6 (inverse
+    iteration with the oracle's solver), a bound of 6.7e-6 at a 1e-12
+    residual.  Modulo a constant the error is bounded by lambda_max / pi^2
+    (pi^2: the lowest non-constant Neumann mode of the unit cube) times the
+    residual, ~1.8e-8 at 1e-12."""
     torch = torch_cuda
     p = W.sphere_ellipsoid_case(96)
     say("manufactured 96")
+    O = oracle.setup(p.xf, p.yf, p.zf, p.bodies)
     flags, st, sol, _ = gpu_setup(torch, p, tol=1e-12)
-    fl = flags.cpu().numpy()
+    fl = O.flags
+    assert np.array_equal(flags.cpu().numpy(), fl)
     rng = np.random.default_rng(12)
     xt = rng.uniform(-1, 1, sol.n_unknowns)
-    xt[~refpy.active_mask(fl, sol.nm)] = 0.0
+    act = refpy.active_mask(fl, sol.nm)
+    xt[~act] = 0.0
     xt[int(np.nonzero(fl & 8)[0][0])] = 0.0
-    xtd = torch.from_numpy(xt).cuda()
-    b = sol.apply(xtd)
-    x, stats = sol.solve_assembled(b)
-    # error <= kappa(A) * relative residual; kappa ~ (12/h_min^2)/(3 pi^2) ~ 1e4
-    # on this stretched 96^3 grid, so 1e-12 buys ~1e-8 (measured 1.02e-8)
-    assert stats.rel_residual <= 1e-12
-    assert rel(x.cpu().numpy(), xt) < 1e-7
+    b = oracle.apply(p.xf, p.yf, p.zf, fl, O.st, xt)
+    x, stats = sol.solve_assembled(torch.from_numpy(b).cuda())
+    x = x.cpu().numpy()
+    res = float(np.linalg.norm(b - oracle.apply(p.xf, p.yf, p.zf, fl, O.st, x)) / np.linalg.norm(b))
+    y = rng.uniform(-1, 1, len(xt))
+    y[~act] = 0.0
+    for _ in range(30):
+        z = oracle.apply(p.xf, p.yf, p.zf, fl, O.st, y)
+        lam = float(np.linalg.norm(z) / np.linalg.norm(y))
+        y = z / np.linalg.norm(z)
+    N = len(fl)
+    fluid = (fl & 1) == 0
+    e = x - xt
+    e = np.where(act, e - e[:N][fluid].mean(), 0.0)
+    t = np.where(act, xt - xt[:N][fluid].mean(), 0.0)
+    err_mc = float(np.linalg.norm(e) / np.linalg.norm(t))
+    say("manufactured 96: residual %.2e (own %.2e), lambda_max %.3e, error %.2e, modulo a constant %.2e" %
+        (res, stats.rel_residual, lam, rel(x, xt), err_mc))
+    assert stats.rel_residual <= 1e-12 and res <= 2e-12
+    assert err_mc < lam / math.pi ** 2 * res
+    assert rel(x, xt) < 6.7e6 * res
 
 
 def test_no_graph_equals_graph(torch_cuda):

@@ -10,6 +10,7 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 from paper_2605_04335_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -92,6 +93,32 @@ def test_mix_equals_alone(P):
     # with 3 slots, some requests ran at the same time
     iv = sorted(r[4][1:] for r in res.values())
     assert any(iv[q + 1][0] < iv[q][1] for q in range(len(iv) - 1))
+
+
+def test_served_results_match_oracle(P):
+    """Requests served together (three slots, arrivals while others run),
+    one of them at the serving workload's sizes (edge >= 128), mixed
+    precision with the tolerance tightened to 1e-10 for the parity check:
+    each result matches the FP64 oracle's 1e-13 solution of the same request
+    to 1e-8 relative L2 after the gauge."""
+    reqs = requests(4, 17) + requests(1, 18, 128, 160)
+    assert max(max(q.shape) for q in reqs) >= 128
+    opts = dict(precision="mixed", tol=1e-10, max_iter=60, max_outer=20)
+    srv = P.Server(hbm_budget=16 << 30, max_slots=3)
+    try:
+        tickets = [srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, **opts) for p in reqs]
+        res = wait_all(P, srv, tickets)
+    finally:
+        srv.close()
+    for q, (p, t) in enumerate(zip(reqs, tickets)):
+        rc, state, x, st, _ = res[t]
+        assert rc == P.IBM_OK and st.rel_residual <= 1e-10
+        O = oracle.setup(p.xf, p.yf, p.zf, p.bodies)
+        xo, _, _, info = oracle.solve_problem(O, p.f, tol=1e-13, maxit=200)
+        assert info.rc == 0
+        e = float(np.linalg.norm(x - xo) / np.linalg.norm(xo))
+        say("request", q, p.shape, len(p.bodies), "bodies: %d iterations, error vs oracle %.2e" % (st.iterations, e))
+        assert e < 1e-8
 
 
 def test_slot_limit_serialises(P):
