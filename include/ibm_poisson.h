@@ -156,6 +156,30 @@ int32_t ibm_classify(const ibm_grid *grid, const ibm_body *bodies, int32_t n_bod
                      ibm_class_stats *st, void *stream);
 
 /*
+ * ibm_classify_noalloc -- ibm_classify for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, results and synchronisation as
+ * ibm_classify, but every device buffer of the call (faces, quantised
+ * centres and vertices, toggle and cut-link bitsets, per-ray markers,
+ * counters) is carved from one fixed array of IBM_CLASSIFY_NOALLOC_MAX_BYTES
+ * in device memory that each GPU the library runs on holds until the process
+ * ends; the call makes no hipMalloc, hipFree or other allocating call.
+ *   scratch_bytes (host, may be NULL): the scratch this input needs.
+ * Needs about N/8 bytes with closed bodies, 3N/8 with membranes, N/2 with
+ * both (N cells), plus 48 bytes per vertex and 12 per triangle (a 512^3
+ * grid with membranes takes 48 MiB of bitsets; closed bodies alone fit up to
+ * about 800^3 cells).  An input that needs more
+ * than the maximum returns IBM_ENOMEM with *scratch_bytes set and nothing
+ * enqueued.  The array keeps the last call's contents (the call clears what
+ * it needs).  Calls that overlap on one GPU (concurrent host threads, or
+ * streams not ordered with each other) race on the shared array: serialise
+ * them.
+ */
+#define IBM_CLASSIFY_NOALLOC_MAX_BYTES (64u << 20)
+int32_t ibm_classify_noalloc(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body, uint8_t *flags_dev,
+                             ibm_class_stats *st, size_t *scratch_bytes, void *stream);
+
+/*
  * ibm_build_ghost_stencils -- ghost-cell boundary rows (Sec. 2.5, module 2;
  * GCM of Mittal et al. 2008): for each closed ghost cell and each membrane
  * ghost unknown, the body intercept (closest point on the body surface of

@@ -102,7 +102,7 @@ EXPORTS = ["ibm_classify", "ibm_build_ghost_stencils", "ibm_stencils_info", "ibm
            "poisson_submit", "poisson_poll", "poisson_server_drain", "poisson_server_destroy", "ibm_last_error",
            "poisson_update", "poisson_solve_from", "ibm_fill_fresh", "ibm_surface_forces",
            "ibm_build_ghost_stencils_bc", "ibm_ad_default_opts", "ibm_ad_setup", "ibm_ad_apply", "ibm_ad_solve",
-           "ibm_ad_destroy", "ibm_hbm_stream", "poisson_kernel_timing"]
+           "ibm_ad_destroy", "ibm_hbm_stream", "poisson_kernel_timing", "ibm_classify_noalloc"]
 
 _lib = None
 
@@ -211,6 +211,27 @@ def classify(xf, yf, zf, bodies, device="cuda"):
     _check(lib().ibm_classify(ctypes.byref(G.g), B.arr, ctypes.c_int32(B.n), _tptr(flags), ctypes.byref(st),
                               _stream()), "ibm_classify")
     return flags, {k: getattr(st, k) for k, _ in st._fields_}
+
+
+CLASSIFY_NOALLOC_MAX_BYTES = 64 << 20
+
+
+def classify_noalloc(xf, yf, zf, bodies, flags=None):
+    """ibm_classify_noalloc: the classification with every device buffer of
+    the call in the library's fixed per-device array (no device allocation
+    in the library).  flags: a device uint8 tensor of N cells to write
+    (allocated here when None).  Returns (flags, counts, scratch bytes)."""
+    import torch
+    G = _GridArgs(xf, yf, zf)
+    B = _BodyArgs(bodies)
+    if flags is None:
+        flags = torch.empty(G.N, dtype=torch.uint8, device="cuda")
+    assert flags.dtype == torch.uint8 and flags.is_cuda and flags.numel() >= G.N
+    st = _ClassStats()
+    need = ctypes.c_size_t()
+    _check(lib().ibm_classify_noalloc(ctypes.byref(G.g), B.arr, ctypes.c_int32(B.n), _tptr(flags), ctypes.byref(st),
+                                      ctypes.byref(need), _stream()), "ibm_classify_noalloc")
+    return flags, {k: getattr(st, k) for k, _ in st._fields_}, need.value
 
 
 def fill_fresh(xf, yf, zf, flags_old, flags_new, x) -> int:

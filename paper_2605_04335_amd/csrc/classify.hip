@@ -255,54 +255,92 @@ __global__ void k_counts(const uint8_t *flags, long long N, unsigned long long *
     if (threadIdx.x < 4) atomicAdd(&cnt[threadIdx.x], s[threadIdx.x]);
 }
 
-}  // namespace
-
-// Host orchestration of the classification.
-void classify(const ibm_grid *grid, const ibm_body *bodies, int n_body, uint8_t *flags, ibm_class_stats *st,
-              hipStream_t s)
+// counters of one classification: pin (minimum), then the four counts
+__global__ void k_init_counters(unsigned long long *dev)
 {
-    HostGrid g = read_grid(grid);
-    IBM_REQUIRE(flags != nullptr, IBM_EINVAL, "null flags");
-    IBM_REQUIRE(n_body >= 0 && (n_body == 0 || bodies != nullptr), IBM_EINVAL, "bad body list");
-    const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
-    double L = 0.0;
-    for (int d = 0; d < 3; ++d) L = std::max(L, g.f[d][g.n[d]] - g.f[d][0]);
-    Lat lat;
-    lat.S = 65536.0 / L;
-    for (int d = 0; d < 3; ++d) lat.lo[d] = g.f[d][0];
+    if (threadIdx.x < 5) dev[threadIdx.x] = threadIdx.x == 0 ? ~0ull : 0ull;
+}
 
-    DBuf<double> df[3];
-    DBuf<long long> qc[3];
+// Device scratch of one classification, carved from one region in 256-byte
+// aligned pieces.  A carve with a null base only measures.
+struct Carve {
+    char *base = nullptr;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t n)
+    {
+        off = (off + 255) / 256 * 256;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+struct BodyScratch {
+    double *dv;
+    int32_t *dt;
+    long long *qv;
+};
+
+struct ClassifyScratch {
+    double *df[3];
+    long long *qc[3];
+    uint32_t *tog = nullptr, *cut[3] = {nullptr, nullptr, nullptr};
+    uint8_t *has = nullptr;
+    unsigned long long *dev;
+    std::vector<BodyScratch> body;
+};
+
+// Every device buffer a classification uses: per axis the faces and the
+// quantised centres; the toggle bitset and per-ray markers (closed bodies);
+// three cut-link bitsets (membranes); per body its vertices, triangles and
+// quantised vertices; the five counters.
+ClassifyScratch carve_classify(Carve &C, const HostGrid &g, const ibm_body *bodies, int n_body, bool any_closed,
+                               bool any_mem)
+{
+    ClassifyScratch S;
+    const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+    const size_t words = (size_t)((N + 31) / 32 + 1);
     for (int d = 0; d < 3; ++d) {
-        upload(df[d], g.f[d], s);
-        qc[d].alloc(g.n[d]);
-        k_quant_centres<<<cdiv(g.n[d], 256), 256, 0, s>>>(df[d].p, g.n[d], lat.lo[d], lat.S, qc[d].p);
-        IBM_LAUNCH_CHECK();
+        S.df[d] = C.take<double>(g.n[d] + 1);
+        S.qc[d] = C.take<long long>(g.n[d]);
     }
-    const long long words = (N + 31) / 32 + 1;
-    k_fill_u8<<<2048, 256, 0, s>>>(flags, N, 0);
-    IBM_LAUNCH_CHECK();
-    bool any_closed = false, any_mem = false;
-    for (int b = 0; b < n_body; ++b) {
-        IBM_REQUIRE(bodies[b].kind == IBM_KIND_CLOSED || bodies[b].kind == IBM_KIND_MEMBRANE, IBM_EINVAL, "bad body kind");
-        (bodies[b].kind == IBM_KIND_CLOSED ? any_closed : any_mem) = true;
-    }
-    DBuf<uint32_t> tog, cut[3];
-    DBuf<uint8_t> has;
     if (any_closed) {
-        tog.alloc(words);
-        has.alloc((size_t)g.n[1] * g.n[2]);
+        S.tog = C.take<uint32_t>(words);
+        S.has = C.take<uint8_t>((size_t)g.n[1] * g.n[2]);
     }
     if (any_mem)
-        for (int d = 0; d < 3; ++d) {
-            cut[d].alloc(words);
-            k_fill_u32<<<2048, 256, 0, s>>>(cut[d].p, words, 0u);
-            IBM_LAUNCH_CHECK();
-        }
+        for (int d = 0; d < 3; ++d) S.cut[d] = C.take<uint32_t>(words);
+    for (int b = 0; b < n_body; ++b) {
+        BodyScratch B;
+        B.dv = C.take<double>((size_t)3 * bodies[b].n_vert);
+        B.dt = C.take<int32_t>((size_t)3 * bodies[b].n_tri);
+        B.qv = C.take<long long>((size_t)3 * bodies[b].n_vert);
+        S.body.push_back(B);
+    }
+    S.dev = C.take<unsigned long long>(5);
+    return S;
+}
+
+struct ClassifyPlan {
+    HostGrid g;
+    bool any_closed = false, any_mem = false;
+    size_t bytes = 0;  // device scratch the classification needs
+};
+
+// Argument checks and the scratch size; nothing touches the device.
+ClassifyPlan plan_classify(const ibm_grid *grid, const ibm_body *bodies, int n_body, const uint8_t *flags)
+{
+    ClassifyPlan P;
+    P.g = read_grid(grid);
+    const HostGrid &g = P.g;
+    IBM_REQUIRE(flags != nullptr, IBM_EINVAL, "null flags");
+    IBM_REQUIRE(n_body >= 0 && (n_body == 0 || bodies != nullptr), IBM_EINVAL, "bad body list");
     for (int b = 0; b < n_body; ++b) {
         const ibm_body &B = bodies[b];
+        IBM_REQUIRE(B.kind == IBM_KIND_CLOSED || B.kind == IBM_KIND_MEMBRANE, IBM_EINVAL, "bad body kind");
+        (B.kind == IBM_KIND_CLOSED ? P.any_closed : P.any_mem) = true;
         IBM_REQUIRE(B.n_vert >= 3 && B.n_tri >= 1 && B.vert && B.tri, IBM_EINVAL, "empty body");
-        std::vector<long long> dummy;
         for (int v = 0; v < 3 * B.n_vert; ++v) {
             int d = v % 3;
             double x = B.vert[v];
@@ -312,50 +350,82 @@ void classify(const ibm_grid *grid, const ibm_body *bodies, int n_body, uint8_t 
         }
         for (int t = 0; t < 3 * B.n_tri; ++t)
             IBM_REQUIRE(B.tri[t] >= 0 && B.tri[t] < B.n_vert, IBM_EGEOM, "triangle index out of range");
-        DBuf<double> dv((size_t)3 * B.n_vert);
-        DBuf<int32_t> dt((size_t)3 * B.n_tri);
-        DBuf<long long> qv((size_t)3 * B.n_vert);
-        IBM_HIP(hipMemcpyAsync(dv.p, B.vert, dv.bytes(), hipMemcpyHostToDevice, s));
-        IBM_HIP(hipMemcpyAsync(dt.p, B.tri, dt.bytes(), hipMemcpyHostToDevice, s));
-        k_quant_verts<<<cdiv(3 * B.n_vert, 256), 256, 0, s>>>(dv.p, B.n_vert, lat, qv.p);
+    }
+    Carve C;
+    (void)carve_classify(C, g, bodies, n_body, P.any_closed, P.any_mem);
+    P.bytes = C.off;
+    return P;
+}
+
+// Host orchestration of the classification; every device buffer of the call
+// comes from `scratch` (at least plan.bytes, 256-byte aligned).
+void classify_with(const ClassifyPlan &plan, const ibm_body *bodies, int n_body, uint8_t *flags, ibm_class_stats *st,
+              char *scratch, hipStream_t s)
+{
+    const HostGrid &g = plan.g;
+    const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
+    double L = 0.0;
+    for (int d = 0; d < 3; ++d) L = std::max(L, g.f[d][g.n[d]] - g.f[d][0]);
+    Lat lat;
+    lat.S = 65536.0 / L;
+    for (int d = 0; d < 3; ++d) lat.lo[d] = g.f[d][0];
+    Carve C;
+    C.base = scratch;
+    ClassifyScratch S = carve_classify(C, g, bodies, n_body, plan.any_closed, plan.any_mem);
+
+    for (int d = 0; d < 3; ++d) {
+        IBM_HIP(hipMemcpyAsync(S.df[d], g.f[d].data(), (g.n[d] + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+        k_quant_centres<<<cdiv(g.n[d], 256), 256, 0, s>>>(S.df[d], g.n[d], lat.lo[d], lat.S, S.qc[d]);
+        IBM_LAUNCH_CHECK();
+    }
+    const long long words = (N + 31) / 32 + 1;
+    k_fill_u8<<<2048, 256, 0, s>>>(flags, N, 0);
+    IBM_LAUNCH_CHECK();
+    if (plan.any_mem)
+        for (int d = 0; d < 3; ++d) {
+            k_fill_u32<<<2048, 256, 0, s>>>(S.cut[d], words, 0u);
+            IBM_LAUNCH_CHECK();
+        }
+    for (int b = 0; b < n_body; ++b) {
+        const ibm_body &B = bodies[b];
+        const BodyScratch &Q = S.body[b];
+        IBM_HIP(hipMemcpyAsync(Q.dv, B.vert, (size_t)3 * B.n_vert * sizeof(double), hipMemcpyHostToDevice, s));
+        IBM_HIP(hipMemcpyAsync(Q.dt, B.tri, (size_t)3 * B.n_tri * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        k_quant_verts<<<cdiv(3 * B.n_vert, 256), 256, 0, s>>>(Q.dv, B.n_vert, lat, Q.qv);
         IBM_LAUNCH_CHECK();
         RayArgs A;
-        for (int d = 0; d < 3; ++d) { A.qc[d] = qc[d].p; A.n[d] = g.n[d]; }
-        A.qv = qv.p;
-        A.tri = dt.p;
+        for (int d = 0; d < 3; ++d) { A.qc[d] = S.qc[d]; A.n[d] = g.n[d]; }
+        A.qv = Q.qv;
+        A.tri = Q.dt;
         A.nt = B.n_tri;
         if (B.kind == IBM_KIND_CLOSED) {
-            k_fill_u32<<<2048, 256, 0, s>>>(tog.p, words, 0u);
-            k_fill_u8<<<256, 256, 0, s>>>(has.p, (long long)g.n[1] * g.n[2], 0);
+            k_fill_u32<<<2048, 256, 0, s>>>(S.tog, words, 0u);
+            k_fill_u8<<<256, 256, 0, s>>>(S.has, (long long)g.n[1] * g.n[2], 0);
             IBM_LAUNCH_CHECK();
-            A.d = 0; A.mode = 0; A.bits = tog.p; A.has = has.p;
+            A.d = 0; A.mode = 0; A.bits = S.tog; A.has = S.has;
             k_rays<<<cdiv(B.n_tri, 64), 64, 0, s>>>(A);
             IBM_LAUNCH_CHECK();
             long long nrays = (long long)g.n[1] * g.n[2];
-            k_ray_parity<<<cdiv(nrays, 128), 128, 0, s>>>(tog.p, has.p, g.n[0], nrays, flags);
+            k_ray_parity<<<cdiv(nrays, 128), 128, 0, s>>>(S.tog, S.has, g.n[0], nrays, flags);
             IBM_LAUNCH_CHECK();
         } else {
             for (int d = 0; d < 3; ++d) {
-                A.d = d; A.mode = 1; A.bits = cut[d].p; A.has = nullptr;
+                A.d = d; A.mode = 1; A.bits = S.cut[d]; A.has = nullptr;
                 k_rays<<<cdiv(B.n_tri, 64), 64, 0, s>>>(A);
                 IBM_LAUNCH_CHECK();
             }
         }
-        // keep the per-body buffers alive until their kernels ran
-        IBM_HIP(hipStreamSynchronize(s));
     }
-    k_flags<<<cdiv(N, 256), 256, 0, s>>>(flags, any_mem ? cut[0].p : nullptr, any_mem ? cut[1].p : nullptr,
-                                         any_mem ? cut[2].p : nullptr, g.n[0], g.n[1], g.n[2], any_mem ? 1 : 0);
-    IBM_LAUNCH_CHECK();
-    DBuf<unsigned long long> dev(5);
-    std::vector<unsigned long long> init = {~0ull, 0, 0, 0, 0};
-    IBM_HIP(hipMemcpyAsync(dev.p, init.data(), 5 * 8, hipMemcpyHostToDevice, s));
-    k_pin<<<2048, 256, 0, s>>>(flags, N, dev.p);
-    k_set_pin<<<1, 64, 0, s>>>(flags, dev.p, N);
-    k_counts<<<1024, 256, 0, s>>>(flags, N, dev.p + 1);
+    k_flags<<<cdiv(N, 256), 256, 0, s>>>(flags, S.cut[0], S.cut[1], S.cut[2], g.n[0], g.n[1], g.n[2],
+                                         plan.any_mem ? 1 : 0);
+    k_init_counters<<<1, 64, 0, s>>>(S.dev);
+    k_pin<<<2048, 256, 0, s>>>(flags, N, S.dev);
+    k_set_pin<<<1, 64, 0, s>>>(flags, S.dev, N);
+    k_counts<<<1024, 256, 0, s>>>(flags, N, S.dev + 1);
     IBM_LAUNCH_CHECK();
     unsigned long long h[5];
-    IBM_HIP(hipMemcpyAsync(h, dev.p, 5 * 8, hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipMemcpyAsync(h, S.dev, 5 * 8, hipMemcpyDeviceToHost, s));
+    // the counts are needed on the host; this also ends every use of the scratch
     IBM_HIP(hipStreamSynchronize(s));
     IBM_REQUIRE(h[0] < (unsigned long long)N, IBM_EGEOM, "no fluid cell outside the membrane ghosts");
     if (st) {
@@ -367,10 +437,58 @@ void classify(const ibm_grid *grid, const ibm_body *bodies, int n_body, uint8_t 
     }
 }
 
+// Scratch of ibm_classify_noalloc: one array per device, for the life of the
+// process.  Its host-side name is not a device address; the address comes
+// from hipGetSymbolAddress, once per device.
+constexpr size_t NOALLOC_BYTES = (size_t)IBM_CLASSIFY_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<char *> g_scratch_ptr;  // per device ordinal, null until looked up
+
+char *device_scratch()
+{
+    int dev = 0;
+    IBM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        IBM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        IBM_REQUIRE(ptr != nullptr, IBM_EHIP, "no device address for the classification scratch");
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+void classify(const ibm_grid *grid, const ibm_body *bodies, int n_body, uint8_t *flags, ibm_class_stats *st,
+              hipStream_t s)
+{
+    const ClassifyPlan plan = plan_classify(grid, bodies, n_body, flags);
+    DBuf<char> ws(plan.bytes);
+    classify_with(plan, bodies, n_body, flags, st, ws.p, s);
+}
+
 }  // namespace ibm
 
 extern "C" int32_t ibm_classify(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body, uint8_t *flags_dev,
                                 ibm_class_stats *st, void *stream)
 {
     return ibm::guarded([&] { ibm::classify(grid, bodies, n_body, flags_dev, st, (hipStream_t)stream); });
+}
+
+extern "C" int32_t ibm_classify_noalloc(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body,
+                                        uint8_t *flags_dev, ibm_class_stats *st, size_t *scratch_bytes, void *stream)
+{
+    return ibm::guarded([&] {
+        const ibm::ClassifyPlan plan = ibm::plan_classify(grid, bodies, n_body, flags_dev);
+        if (scratch_bytes) *scratch_bytes = plan.bytes;
+        IBM_REQUIRE(plan.bytes <= ibm::NOALLOC_BYTES, IBM_ENOMEM,
+                    "ibm_classify_noalloc: this grid and these bodies need " + std::to_string(plan.bytes) +
+                        " bytes of scratch, above its fixed " + std::to_string(ibm::NOALLOC_BYTES) +
+                        " (use ibm_classify)");
+        ibm::classify_with(plan, bodies, n_body, flags_dev, st, ibm::device_scratch(), (hipStream_t)stream);
+    });
 }
