@@ -450,6 +450,9 @@ def main():
                     help="HBM budget (GB) of a second run at the highest rate, where admission binds; 0: skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with three plain 1 GiB stream copies (reference for HBM byte counters)")
+    ap.add_argument("--profile", default="none", choices=["none", "mixed", "stream"],
+                    help="profiler runs: 'mixed' times only the mixed form (--warmup and --steps solves and one "
+                         "with per-launch sweep timing), 'stream' only the streaming ceiling")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PPE solve runs on a single MI355X; "
@@ -462,6 +465,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile == "stream":
+        out = {"hbm_ceiling": hbm_ceiling(P)}
+        if args.copy_calibration:
+            P.hbm_stream(P.STREAM_COPY, 1 << 30, 3)
+        print(json.dumps(out), flush=True)
+        return
     p, desc = make_problem(args.config)
     nx, ny, nz = p.shape
     N = p.npts
@@ -472,11 +481,22 @@ def main():
     flags, cst = P.classify(p.xf, p.yf, p.zf, p.bodies)
     st = P.build_ghost_stencils(p.xf, p.yf, p.zf, p.bodies, flags)
     ng, nm, nfb = st.info()
+    f = torch.from_numpy(p.f).to(dev)
+    if args.profile == "mixed":
+        solm = P.Solver(p.xf, p.yf, p.zf, flags, st, precision=P.PREC_MIXED, tol=p.tol, max_iter=60)
+        for _ in range(args.warmup):
+            solm.solve(f)
+        msm, xm, sm = time_solves(solm, f, args.steps)
+        roofm = sweep_roofline(P, solm, f, 4, N, measured_traffic(key, "f32"))
+        if args.copy_calibration:
+            P.hbm_stream(P.STREAM_COPY, 1 << 30, 3)
+        print(json.dumps({"mixed": {"ms_per_solve": round(msm, 3), "iterations": sm.iterations,
+                                    "outer_steps": sm.outer_steps, "roofline": roofm}}), flush=True)
+        return
     sol = P.Solver(p.xf, p.yf, p.zf, flags, st, precision=P.PREC_FP64, tol=p.tol, max_iter=200)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     log("setup %.2f s: ghosts %d, membrane ghosts %d, fallback %d" % (setup_s, ng, nm, nfb))
-    f = torch.from_numpy(p.f).to(dev)
 
     # ---- headline: the FP64 solve
     for _ in range(args.warmup):
