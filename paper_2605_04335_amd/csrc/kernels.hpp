@@ -466,6 +466,66 @@ __global__ void __launch_bounds__(TPB) k_csweep(Lv L, Geo G, T *__restrict__ x, 
     const uint8_t *fc = L.f + (long long)c * L.Nh;
     const TB *bc = b + (long long)c * L.Nh;
     const Col0 q = col0(L, c, h, j);
+    if constexpr (ZMODE == 0) {
+        // ordinary sweep: the other colour's values at (h, j) in planes k-1,
+        // k, k+1 kept in registers (the centre is an x neighbour, the planes
+        // above and below the z neighbours), every load of a step issued
+        // unconditionally before any arithmetic (the planes beyond the walls
+        // read clamped indices: their mask bits close those faces), 32-bit
+        // offsets from plane-uniform bases.  Same arithmetic as below.
+        constexpr int UW = 2;
+        const uint32_t pl = (uint32_t)(L.H * L.ny);
+        const int kb = max(k0 - 1, 0);
+        const T *xb = xo + (long long)pl * kb;
+        const TB *bp = bc + (long long)pl * kb;
+        const uint8_t *fb = fc + (long long)pl * kb;
+        T *xw = xc + (long long)pl * kb;
+        const uint32_t col = (uint32_t)(h + L.H * j);
+        const int ox0 = q.oxp[0] + q.oxm[0], ox1 = q.oxp[1] + q.oxm[1];
+        auto zs = [&](int k) { return col + pl * (uint32_t)(k - kb); };
+        double cprev = ldu(xb, zs(max(k0 - 1, 0))), ccur = ldu(xb, zs(k0));
+        for (int ks = k0; ks < k1; ks += UW) {
+            double cn[UW], xs[UW], yp[UW], ym[UW], bb[UW], zp[UW], zm[UW];
+            uint8_t fl[UW];
+#pragma unroll
+            for (int u = 0; u < UW; ++u) {
+                const int k = min(ks + u, k1 - 1);
+                const uint32_t s = zs(k);
+                cn[u] = ldu(xb, zs(min(k + 1, L.nz - 1)));
+                xs[u] = ldu(xb, s + (uint32_t)((k & 1) ? ox1 : ox0));
+                yp[u] = ldu(xb, s + (uint32_t)(int)q.oyp);
+                ym[u] = ldu(xb, s + (uint32_t)(int)q.oym);
+                fl[u] = ldu(fb, s);
+                bb[u] = ld(bp, (long long)s);
+                zp[u] = L.cp[2][k];
+                zm[u] = L.cm[2][k];
+            }
+#pragma unroll
+            for (int u = 0; u < UW; ++u) {
+                const int k = ks + u;
+                if (k >= k1) continue;
+                const double cc = u == 0 ? ccur : cn[u - 1];
+                const double cmv = u == 0 ? cprev : (u == 1 ? ccur : cn[u - 2]);
+                const uint32_t s = zs(k);
+                const int i = 2 * h + ((c + j + k) & 1);
+                const uint8_t f = fl[u];
+                if (!(f & CM_ACT) || i >= L.nx) continue;
+                const bool t = k & 1;
+                const double cpx = (f & CM_PX) ? (t ? q.cpx[1] : q.cpx[0]) : 0.0;
+                const double cmx = (f & CM_MX) ? (t ? q.cmx[1] : q.cmx[0]) : 0.0;
+                const double cpy = (f & CM_PY) ? q.cpy : 0.0, cmy = (f & CM_MY) ? q.cmy : 0.0;
+                const double czp = (f & CM_PZ) ? zp[u] : 0.0, czm = (f & CM_MZ) ? zm[u] : 0.0;
+                const int oxp = t ? q.oxp[1] : q.oxp[0], oxm = t ? q.oxm[1] : q.oxm[0];
+                const double xpv = oxp == 0 ? cc : xs[u], xmv = oxm == 0 ? cc : xs[u];
+                const double dg = cpx + cmx + cpy + cmy + czp + czm;
+                const double nb = cpx * xpv + cmx * xmv + cpy * yp[u] + cmy * ym[u] + czp * cn[u] + czm * cmv;
+                st(xw, (long long)s, dg > 0.0 ? (nb - (bb[u] - mu)) / dg : 0.0);
+            }
+            cprev = cn[UW - 2];
+            ccur = cn[UW - 1];
+        }
+        return;
+    }
     const long long pl = (long long)L.H * L.ny;
     const long long col = h + (long long)L.H * j;
     for (int kb = k0; kb < k1; kb += UC) {

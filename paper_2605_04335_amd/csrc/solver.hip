@@ -928,7 +928,11 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
         }
     }
     IBM_REQUIRE(c->lv[0].geo.nb <= PSTRIDE - 2048, IBM_EINVAL, "grid too large");
-    for (auto &L : c->lv) IBM_REQUIRE(L.geo.nb <= PSTRIDE && L.geon.nb <= PSTRIDE, IBM_EINVAL, "grid too large");
+    for (auto &L : c->lv) {
+        IBM_REQUIRE(L.geo.nb <= PSTRIDE && L.geon.nb <= PSTRIDE, IBM_EINVAL, "grid too large");
+        IBM_REQUIRE(plane_span_ok((long long)L.H * L.n[1], L.geo.kz, sizeof(double)), IBM_EINVAL,
+                    "grid planes too large for the sweeps' 32-bit offsets");
+    }
     c->Wc = make_walk(c->N2);
     c->sc.alloc(S_COUNT);
     c->part.alloc((size_t)PSTRIDE * 4);
