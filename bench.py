@@ -132,8 +132,10 @@ def sweep_source_digest():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2605_04335_amd", "csrc", "kernels.hpp")).read()
     a = src.index("struct Col0 {")
-    b = src.index("// First level-0 half-sweep of a V-cycle, from a zero iterate")
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    b = src.index("// sum of coefficient * other-colour neighbour at slot s of plane k")
+    c = src.index("// Level-0 Gauss-Seidel half-sweep of colour c (ordinary mode)")
+    d = src.index("// First level-0 half-sweep of a V-cycle, from a zero iterate")
+    return hashlib.sha256((src[a:b] + src[c:d]).encode()).hexdigest()[:16]
 
 
 def solver_source_digest():

@@ -657,7 +657,8 @@ __global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T 
 
 // First level-0 half-sweep of a V-cycle, from a zero iterate: every regular
 // cell of colour c gets -b/diag (its neighbours are zero), every other slot
-// of both colours gets 0.
+// of both colours gets 0.  32-bit offsets from the tile's first plane,
+// non-temporal stores (as k0_sweep).
 template <class T>
 __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_s, T *__restrict__ xc,
                                                      T *__restrict__ xo, const T *__restrict__ bc,
@@ -667,9 +668,14 @@ __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_
     int h, j, k0, k1;
     if (!geo_tile(G, h, j, k0, k1)) return;
     const Col0 q = col0(L, c, h, j);
-    const long long pl = (long long)L.H * L.ny;
-    const long long col = h + (long long)L.H * j;
+    const uint32_t pl = (uint32_t)(L.H * L.ny);
+    const long long base = (long long)pl * k0;
+    const T *bp = bc + base;
+    const uint8_t *fb = fc + base;
+    T *xw = xc + base, *xz = xo + base;
+    const uint32_t col = (uint32_t)(h + L.H * j);
     const double snk = pin_s >= 0 ? sink[0] : 0.0;
+    const long long pin_rel = pin_s >= 0 ? pin_s - base : -1;
     // the RHS, masks and z coefficients of UZ planes are loaded before any is used
     constexpr int UZ = 4;
     for (int kb = k0; kb < k1; kb += UZ) {
@@ -678,9 +684,9 @@ __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_
 #pragma unroll
         for (int u = 0; u < UZ; ++u) {
             const int k = min(kb + u, k1 - 1);
-            const long long s = col + pl * k;
-            bv[u] = ld(bc, s);
-            fv[u] = fc[s];
+            const uint32_t s = col + pl * (uint32_t)(k - k0);
+            bv[u] = ldu(bp, s);
+            fv[u] = ldu(fb, s);
             zp[u] = L.cp[2][k];
             zm[u] = L.cm[2][k];
         }
@@ -688,13 +694,13 @@ __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_
         for (int u = 0; u < UZ; ++u) {
             const int k = kb + u;
             if (k >= k1) continue;
-            const long long s = col + pl * k;
+            const uint32_t s = col + pl * (uint32_t)(k - k0);
             const bool t = k & 1;
             const double dg = (t ? q.cpx[1] : q.cpx[0]) + (t ? q.cmx[1] : q.cmx[0]) + q.cpy + q.cmy + zp[u] + zm[u];
             double b0 = bv[u];
-            if (s == pin_s) b0 -= snk;
-            st(xc, s, (fv[u] & (F_SOLID | F_MGHOST)) ? 0.0 : -b0 / dg);
-            st(xo, s, 0.0);
+            if ((long long)s == pin_rel) b0 -= snk;
+            st_nt(xw + s, (T)((fv[u] & (F_SOLID | F_MGHOST)) ? 0.0 : -b0 / dg));
+            st_nt(xz + s, (T)0.0);
         }
     }
 }
@@ -768,7 +774,7 @@ __global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, con
                     double o;
                     if (apply_out<T, MODE, RES>(f[u][cc], xv[u][cc], nb[u][cc], dg[u][cc], bv[u][cc], sc, pin, sink,
                                                 o)) {
-                        st(y, sc, o);
+                        st_nt(y + sc, (T)o);  // y is next read by another kernel, long after it left the caches
                         const double yo = round_to<T>(o);  // the stored value
                         if (ND >= 1) a0 += u1v[u][cc] * yo;
                         if (ND >= 2) a1 += (u2 ? u2v[u][cc] : yo) * yo;
