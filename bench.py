@@ -211,67 +211,69 @@ def serving_bench(P, rates, nreq, seed=5, slots=16, budget=64 << 30):
 
     # one warm-up request outside the measurement (first-use costs of the runtime)
     srv = P.Server(hbm_budget=budget, max_slots=slots)
-    w = make(10 ** 6, 1)[0]
-    t = srv.submit(w.xf, w.yf, w.zf, w.bodies, w.f, precision="mixed", tol=1e-8)
-    while srv.poll(t, want_x=False)[0] == P.IBM_EAGAIN:
-        time.sleep(0.001)
-    out = []
-    for rate in rates:
-        reqs = make(10000 * int(rate), nreq)  # the same requests for a rate in every run
-        arr = np.cumsum(np.random.default_rng(seed + int(rate)).exponential(1.0 / rate, nreq))
-        pending, done = {}, []
-        t0 = time.perf_counter()
-        q = 0
-        while q < nreq or pending:
-            now = time.perf_counter() - t0
-            while q < nreq and arr[q] <= now:
-                p = reqs[q]
-                pending[srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, precision="mixed", tol=1e-8)] = p.npts
-                q += 1
-            for tk in list(pending):
-                rc, state, _, st, tm = srv.poll(tk, want_x=False)
-                if rc == P.IBM_EAGAIN:
-                    continue
-                done.append((tm.submit_ms, tm.done_ms, pending.pop(tk), rc, st.rel_residual, tm.admit_ms,
-                             tm.setup_ms, tm.solve_ms, tm.cache_hit))
-            time.sleep(0.0005)
-        del reqs
-        lat = np.array([d[1] - d[0] for d in done])
-        span_s = (max(d[1] for d in done) - min(d[0] for d in done)) / 1e3
-        pts = sum(d[2] for d in done)
-        ok = sum(1 for d in done if d[3] == 0 and d[4] <= 1e-8)
-        queue = np.array([d[5] - d[0] for d in done])
-        setup = np.array([d[6] for d in done])
-        solve = np.array([d[7] for d in done])
-        rest = lat - queue - setup - solve
-        # device occupancy: a request holds the device from admission to
-        # completion; the share of the span with at least one admitted
-        # request, and the mean number admitted at once
-        iv = sorted((d[5], d[1]) for d in done)
-        busy, cur0, cur1 = 0.0, None, None
-        for a0, a1 in iv:
-            if cur1 is None or a0 > cur1:
-                if cur1 is not None:
-                    busy += cur1 - cur0
-                cur0, cur1 = a0, a1
-            else:
-                cur1 = max(cur1, a1)
-        if cur1 is not None:
-            busy += cur1 - cur0
-        span_ms = span_s * 1e3
-        out.append({"rate_req_s": rate, "requests": nreq, "ok": ok, "p50_ms": round(float(np.percentile(lat, 50)), 2),
-                    "p99_ms": round(float(np.percentile(lat, 99)), 2), "solves_s": round(nreq / span_s, 2),
-                    "Mpts_s": round(pts / span_s / 1e6, 1), "cache_hits": int(sum(d[8] for d in done)),
-                    "mean_ms": {"queue": round(float(queue.mean()), 2), "setup": round(float(setup.mean()), 2),
-                                "solve": round(float(solve.mean()), 2), "release": round(float(rest.mean()), 2)},
-                    "busy_frac": round(busy / span_ms, 3),
-                    "mean_active": round(float(sum(d[1] - d[5] for d in done)) / span_ms, 2),
-                    "mean_Mpts_per_request": round(pts / nreq / 1e6, 2)})
-        log("serve rate %g req/s: p50 %.1f ms p99 %.1f ms, %.1f solves/s, %.0f Mpts/s, %d/%d ok; mean queue %.1f "
-            "set-up %.1f solve %.1f release %.1f ms; busy %.2f, %.2f active" %
-            (rate, out[-1]["p50_ms"], out[-1]["p99_ms"], out[-1]["solves_s"], out[-1]["Mpts_s"], ok, nreq,
-             queue.mean(), setup.mean(), solve.mean(), rest.mean(), out[-1]["busy_frac"], out[-1]["mean_active"]))
-    srv.close()
+    try:  # the server's threads end with it, also when a leg fails
+        w = make(10 ** 6, 1)[0]
+        t = srv.submit(w.xf, w.yf, w.zf, w.bodies, w.f, precision="mixed", tol=1e-8)
+        while srv.poll(t, want_x=False)[0] == P.IBM_EAGAIN:
+            time.sleep(0.001)
+        out = []
+        for rate in rates:
+            reqs = make(10000 * int(rate), nreq)  # the same requests for a rate in every run
+            arr = np.cumsum(np.random.default_rng(seed + int(rate)).exponential(1.0 / rate, nreq))
+            pending, done = {}, []
+            t0 = time.perf_counter()
+            q = 0
+            while q < nreq or pending:
+                now = time.perf_counter() - t0
+                while q < nreq and arr[q] <= now:
+                    p = reqs[q]
+                    pending[srv.submit(p.xf, p.yf, p.zf, p.bodies, p.f, precision="mixed", tol=1e-8)] = p.npts
+                    q += 1
+                for tk in list(pending):
+                    rc, state, _, st, tm = srv.poll(tk, want_x=False)
+                    if rc == P.IBM_EAGAIN:
+                        continue
+                    done.append((tm.submit_ms, tm.done_ms, pending.pop(tk), rc, st.rel_residual, tm.admit_ms,
+                                 tm.setup_ms, tm.solve_ms, tm.cache_hit))
+                time.sleep(0.0005)
+            del reqs
+            lat = np.array([d[1] - d[0] for d in done])
+            span_s = (max(d[1] for d in done) - min(d[0] for d in done)) / 1e3
+            pts = sum(d[2] for d in done)
+            ok = sum(1 for d in done if d[3] == 0 and d[4] <= 1e-8)
+            queue = np.array([d[5] - d[0] for d in done])
+            setup = np.array([d[6] for d in done])
+            solve = np.array([d[7] for d in done])
+            rest = lat - queue - setup - solve
+            # device occupancy: a request holds the device from admission to
+            # completion; the share of the span with at least one admitted
+            # request, and the mean number admitted at once
+            iv = sorted((d[5], d[1]) for d in done)
+            busy, cur0, cur1 = 0.0, None, None
+            for a0, a1 in iv:
+                if cur1 is None or a0 > cur1:
+                    if cur1 is not None:
+                        busy += cur1 - cur0
+                    cur0, cur1 = a0, a1
+                else:
+                    cur1 = max(cur1, a1)
+            if cur1 is not None:
+                busy += cur1 - cur0
+            span_ms = span_s * 1e3
+            out.append({"rate_req_s": rate, "requests": nreq, "ok": ok, "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 2), "solves_s": round(nreq / span_s, 2),
+                        "Mpts_s": round(pts / span_s / 1e6, 1), "cache_hits": int(sum(d[8] for d in done)),
+                        "mean_ms": {"queue": round(float(queue.mean()), 2), "setup": round(float(setup.mean()), 2),
+                                    "solve": round(float(solve.mean()), 2), "release": round(float(rest.mean()), 2)},
+                        "busy_frac": round(busy / span_ms, 3),
+                        "mean_active": round(float(sum(d[1] - d[5] for d in done)) / span_ms, 2),
+                        "mean_Mpts_per_request": round(pts / nreq / 1e6, 2)})
+            log("serve rate %g req/s: p50 %.1f ms p99 %.1f ms, %.1f solves/s, %.0f Mpts/s, %d/%d ok; mean queue %.1f "
+                "set-up %.1f solve %.1f release %.1f ms; busy %.2f, %.2f active" %
+                (rate, out[-1]["p50_ms"], out[-1]["p99_ms"], out[-1]["solves_s"], out[-1]["Mpts_s"], ok, nreq,
+                 queue.mean(), setup.mean(), solve.mean(), rest.mean(), out[-1]["busy_frac"], out[-1]["mean_active"]))
+    finally:
+        srv.close()
     return {"workload": "Poisson arrivals, edge log-uniform [64, 384], cube or 2:1:1, 1-4 bodies (spheres, "
                         "ellipsoids, plates), noise RHS, mixed MG-BiCGSTAB to 1e-8; distinct requests per rate",
             "max_slots": slots, "hbm_budget_GB": budget >> 30, "sweep": out}

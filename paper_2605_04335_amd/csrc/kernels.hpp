@@ -708,10 +708,10 @@ __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_
 // Level-0 operator on the regular cells of both colours: y = A x, or
 // y = b - A x with the sink at the pin (RES); membrane cells are left to the
 // sparse kernel, solid cells get 0.  Dots of y with u1, u2 (u2 NULL: with y
-// itself).  Both colours' loads of a plane are issued together.
-template <class T, int MODE, bool RES>
-__device__ __forceinline__ bool apply_out(uint8_t f, double xv, double nsum, double dg, double bv, long long s,
-                                          long long pin, const double *sink, double &out)
+// itself).
+template <int MODE, bool RES>
+__device__ __forceinline__ bool apply_out(uint8_t f, double xv, double nsum, double dg, double bv, bool is_pin,
+                                          const double *sink, double &out)
 {
     if (f & F_MGHOST) return false;
     if (f & F_SOLID) {
@@ -719,10 +719,10 @@ __device__ __forceinline__ bool apply_out(uint8_t f, double xv, double nsum, dou
         return true;
     }
     double axv = nsum - dg * xv;
-    if (s == pin && MODE == M_PINNED) axv = -dg * xv;
-    if (s == pin && MODE == M_PINZERO) axv = 0.0;
+    if (is_pin && MODE == M_PINNED) axv = -dg * xv;
+    if (is_pin && MODE == M_PINZERO) axv = 0.0;
     if (RES) {
-        if (s == pin && sink) bv -= sink[0];
+        if (is_pin && sink) bv -= sink[0];
         out = bv - axv;
     } else {
         out = axv;
@@ -730,56 +730,120 @@ __device__ __forceinline__ bool apply_out(uint8_t f, double xv, double nsum, dou
     return true;
 }
 
+// Each thread walks the planes of its (h, j) column for both colours.  The
+// cell of one colour and the other colour's slot at the same (h, j, k) are x
+// neighbours, and the other colour's slots at (h, j, k -/+ 1) are its z
+// neighbours, so the centres of both colours in planes k-1, k, k+1 stay in
+// registers and a plane costs one new centre per colour plus the outer x
+// neighbour and the two y neighbours.  As in the half-sweep, every load of a
+// step is issued unconditionally before any arithmetic (a wall reads the
+// cell's partner slot, with a zero coefficient), and addresses are 32-bit
+// offsets from block-uniform bases; this keeps the kernel at about 90 VGPRs
+// in FP64 (5 waves per SIMD) where indexing each neighbour with 64-bit
+// addresses took over 130 (3 waves).  Two planes per step.
 template <class T, int MODE, bool RES, int ND>
 __global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, const T *__restrict__ x, T *__restrict__ y,
                                                  const T *__restrict__ b, const double *__restrict__ sink,
                                                  const T *__restrict__ u1, const T *__restrict__ u2, double *part,
                                                  int pstride)
 {
+    constexpr int UA = 2;
     double a0 = 0.0, a1 = 0.0;
     int h, j, k0, k1;
     if (geo_tile(G, h, j, k0, k1)) {
-        const long long pl = (long long)L.H * L.ny, Nh = L.Nh;
-        const long long col = h + (long long)L.H * j;
-        const Col0 q0 = col0(L, 0, h, j), q1 = col0(L, 1, h, j);
-        // UA planes per step; every load of a step is issued before any store
-        constexpr int UA = 2;
-        for (int kb = k0; kb < k1; kb += UA) {
-            uint8_t f[UA][2];
-            double xv[UA][2], nb[UA][2], dg[UA][2], bv[UA][2], u1v[UA][2], u2v[UA][2];
+        const uint32_t pl = (uint32_t)(L.H * L.ny);
+        const int kb = max(k0 - 1, 0);
+        const long long base = (long long)pl * kb, Nh = L.Nh;
+        const T *xb[2] = {x + base, x + Nh + base};
+        const uint8_t *fb[2] = {L.f + base, L.f + Nh + base};
+        // (pointers of operands a variant does not read are never dereferenced)
+        const T *ub[2] = {ND >= 1 ? u1 + base : x + base, ND >= 1 ? u1 + Nh + base : x + Nh + base};
+        const T *u2p = ND >= 2 ? (u2 ? u2 : u1) : x;  // without u2 the second dot reads u1 again (unused)
+        const T *vb[2] = {u2p + base, u2p + Nh + base};
+        const T *bb[2] = {RES ? b + base : x + base, RES ? b + Nh + base : x + Nh + base};
+        T *yb[2] = {y + base, y + Nh + base};
+        const long long prel[2] = {pin - base, pin - Nh - base};
+        const uint32_t col = (uint32_t)(h + L.H * j);
+        // x coefficients of the pair's cells i = 2h + e and the offset of
+        // each one's outer x neighbour (0: the partner, at a wall)
+        double cpe[2], cme[2];
+        int ope[2], ome[2], oxe[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int i = 2 * h + e;
+            const bool xp = i + 1 < L.nx, xm = i > 0 && i < L.nx;
+            cpe[e] = xp ? L.cp[0][i] : 0.0;
+            cme[e] = xm ? L.cm[0][i] : 0.0;
+            ope[e] = xp ? e : 0;
+            ome[e] = xm ? e - 1 : 0;
+            oxe[e] = ope[e] + ome[e];
+        }
+        const double cpy = j + 1 < L.ny ? L.cp[1][j] : 0.0, cmy = j > 0 ? L.cm[1][j] : 0.0;
+        const int oyp = j + 1 < L.ny ? L.H : 0, oym = j > 0 ? -L.H : 0;
+        auto zo = [&](int kk) { return pl * (uint32_t)(kk - kb); };
+        // both colours' centres in planes k-1 and k (below the bottom wall:
+        // plane k itself)
+        double cm0[2], cc0[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            cm0[c] = ldu(xb[c], col + zo(max(k0 - 1, 0)));
+            cc0[c] = ldu(xb[c], col + zo(k0));
+        }
+        for (int ks = k0; ks < k1; ks += UA) {
+            double cn[UA][2], xo[UA][2], yp[UA][2], ym[UA][2], uv[UA][2], wv[UA][2], bv[UA][2], czp[UA], czm[UA];
+            uint8_t fv[UA][2];
 #pragma unroll
             for (int u = 0; u < UA; ++u) {
-                const int k = min(kb + u, k1 - 1);
-                const long long s = col + pl * k, t = Nh + s;
-                f[u][0] = L.f[s];
-                f[u][1] = L.f[t];
-                xv[u][0] = ld(x, s);
-                xv[u][1] = ld(x, t);
-                nb[u][0] = col0_sum(L, q0, x + Nh, s, k, pl, dg[u][0]);
-                nb[u][1] = col0_sum(L, q1, x, s, k, pl, dg[u][1]);
-                bv[u][0] = RES ? ld(b, s) : 0.0;
-                bv[u][1] = RES ? ld(b, t) : 0.0;
-                u1v[u][0] = ND >= 1 ? ld(u1, s) : 0.0;
-                u1v[u][1] = ND >= 1 ? ld(u1, t) : 0.0;
-                u2v[u][0] = (ND >= 2 && u2) ? ld(u2, s) : 0.0;
-                u2v[u][1] = (ND >= 2 && u2) ? ld(u2, t) : 0.0;
+                const int k = min(ks + u, k1 - 1);
+                const uint32_t s = col + zo(k);
+                const int p0 = (j ^ k) & 1;  // colour 0 sits at i = 2h + p0, colour 1 at 2h + 1 - p0
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int e = c ? 1 - p0 : p0;
+                    cn[u][c] = ldu(xb[c], col + zo(min(k + 1, L.nz - 1)));  // centre of plane k+1
+                    xo[u][c] = ldu(xb[1 - c], s + (uint32_t)oxe[e]);
+                    yp[u][c] = ldu(xb[1 - c], s + (uint32_t)oyp);
+                    ym[u][c] = ldu(xb[1 - c], s + (uint32_t)oym);
+                    fv[u][c] = ldu(fb[c], s);
+                    uv[u][c] = ND >= 1 ? (double)ldu(ub[c], s) : 0.0;
+                    wv[u][c] = ND >= 2 ? (double)ldu(vb[c], s) : 0.0;
+                    bv[u][c] = RES ? (double)ldu(bb[c], s) : 0.0;
+                }
+                czp[u] = L.cp[2][k];  // zero at the walls
+                czm[u] = L.cm[2][k];
             }
 #pragma unroll
             for (int u = 0; u < UA; ++u) {
-                if (kb + u >= k1) continue;
-                const long long s0 = col + pl * (kb + u);
+                const int k = ks + u;
+                if (k >= k1) continue;
+                const uint32_t s = col + zo(k);
+                const int p0 = (j ^ k) & 1;
 #pragma unroll
-                for (int cc = 0; cc < 2; ++cc) {
-                    const long long sc = s0 + (cc ? Nh : 0);
-                    double o;
-                    if (apply_out<T, MODE, RES>(f[u][cc], xv[u][cc], nb[u][cc], dg[u][cc], bv[u][cc], sc, pin, sink,
-                                                o)) {
-                        st_nt(y + sc, (T)o);  // y is next read by another kernel, long after it left the caches
-                        const double yo = round_to<T>(o);  // the stored value
-                        if (ND >= 1) a0 += u1v[u][cc] * yo;
-                        if (ND >= 2) a1 += (u2 ? u2v[u][cc] : yo) * yo;
+                for (int c = 0; c < 2; ++c) {
+                    const int e = c ? 1 - p0 : p0;
+                    const int o = 1 - c;
+                    // the other colour's centres: plane k (x partner), k-1 and k+1 (z)
+                    const double pc = u == 0 ? cc0[o] : cn[u - 1][o];
+                    const double pm = u == 0 ? cm0[o] : (u == 1 ? cc0[o] : cn[u - 2][o]);
+                    const double pp = cn[u][o];
+                    const double xpv = ope[e] == 0 ? pc : xo[u][c], xmv = ome[e] == 0 ? pc : xo[u][c];
+                    const double nsum = cpe[e] * xpv + cme[e] * xmv + cpy * yp[u][c] + cmy * ym[u][c] + czp[u] * pp +
+                                        czm[u] * pm;
+                    const double dg = cpe[e] + cme[e] + cpy + cmy + czp[u] + czm[u];
+                    const double xv = u == 0 ? cc0[c] : cn[u - 1][c];
+                    double out;
+                    if (apply_out<MODE, RES>(fv[u][c], xv, nsum, dg, bv[u][c], (long long)s == prel[c], sink, out)) {
+                        st_nt(yb[c] + s, (T)out);  // y is next read by another kernel, long after it left the caches
+                        const double yo = round_to<T>(out);  // the stored value
+                        if (ND >= 1) a0 += uv[u][c] * yo;
+                        if (ND >= 2) a1 += (u2 ? wv[u][c] : yo) * yo;
                     }
                 }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                cm0[c] = cn[UA - 2][c];
+                cc0[c] = cn[UA - 1][c];
             }
         }
     }

@@ -212,10 +212,16 @@ void poisson_server::run_request(Request *r)
     } else {
         used -= r->footprint;
     }
+    if (!gone.empty()) {
+        // evicted set-ups are released outside the lock but before this
+        // worker counts as finished, so that poisson_server_destroy returns
+        // only once no worker touches the device any more
+        lk.unlock();
+        for (poisson_ctx *c : gone) poisson_destroy(c);
+        lk.lock();
+    }
     --active;
     cv.notify_all();
-    lk.unlock();
-    for (poisson_ctx *c : gone) poisson_destroy(c);
 }
 
 void poisson_server::schedule()
