@@ -87,13 +87,13 @@ struct Walk {
     long long per;     // chunks per XCD
     int nb;            // blocks (multiple of 8)
 };
-inline Walk make_walk(long long n)
+inline Walk make_walk(long long n, long long maxb = MAXB)
 {
     Walk w;
     w.n = n;
     w.chunks = (n + TPB - 1) / TPB;
     long long b = (w.chunks + 7) / 8 * 8;
-    if (b > MAXB) b = MAXB;
+    if (b > maxb) b = maxb;
     if (b < 8) b = 8;
     w.nb = (int)b;
     w.per = (w.chunks + 7) / 8;
@@ -2180,9 +2180,19 @@ __global__ void __launch_bounds__(TPB) k_from_split(Lv L, Walk W, const TA *spl,
 __device__ double block_sum_all(const double *part, int n)
 {
     __shared__ double sm[1024];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
-    sm[threadIdx.x] = s;
+    // four independent running sums per thread keep four loads in flight
+    // (up to ~130k partials); fixed order, so the result is reproducible
+    const int bd = blockDim.x;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int i = threadIdx.x;
+    for (; i + 3 * bd < n; i += 4 * bd) {
+        s4[0] += part[i];
+        s4[1] += part[i + bd];
+        s4[2] += part[i + 2 * bd];
+        s4[3] += part[i + 3 * bd];
+    }
+    for (; i < n; i += bd) s4[0] += part[i];
+    sm[threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];

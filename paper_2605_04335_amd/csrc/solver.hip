@@ -29,7 +29,12 @@
 namespace ibm {
 namespace {
 
-constexpr int PSTRIDE = 16384 + 2048;  // partial slots per reduction: stencil or walk blocks, then sparse blocks
+// The Krylov vector updates run one block per 256 groups of four unknowns up
+// to W4MAXB blocks (a 512^3 vector: 131072 blocks, one group per thread):
+// against a 4096-block walk this measured 3% (x/r update) to 11% (p update)
+// faster in FP64 and 11-14% in FP32.  Their block partials set the stride.
+constexpr int W4MAXB = 131072;
+constexpr int PSTRIDE = W4MAXB + 2048;  // partial slots per reduction: stencil or walk blocks, then sparse blocks
 constexpr int XB = 1024;               // cap on blocks of the sparse row kernels
 
 inline int sparse_blocks(long long n) { return (int)std::max<long long>(1, std::min<long long>(XB, (n + TPB - 1) / TPB)); }
@@ -795,7 +800,7 @@ void setup_geometry(poisson_ctx &c, const uint8_t *flags, const ibm_stencils *st
     const bool first = !c.x.p;
     c.Nt = Nt;
     c.W0 = make_walk(Nt);
-    c.W4 = make_walk((Nt + 3) / 4);
+    c.W4 = make_walk((Nt + 3) / 4, W4MAXB);
     const long long cap = first ? Nt : Nt + nm / 4 + 1024;
     DBuf<double> *dv[] = {&c.x, &c.r, &c.b, &c.t, &c.rh, &c.p, &c.v, &c.ph, &c.sh, &c.rsp, &c.d64, &c.r2};
     DBuf<float> *fv[] = {&c.fr, &c.frh, &c.fp, &c.fv, &c.fph, &c.fsh, &c.ft, &c.frsp};
