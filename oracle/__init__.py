@@ -24,7 +24,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ibm_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# IBM_ORACLE_LIB selects another build of the same source (the sanitizer
+# test loads an ASan/UBSan build through it)
+_LIB = os.environ.get("IBM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 F_SOLID, F_GHOST, F_MGHOST, F_PIN = 1, 2, 4, 8
 F_CUTX, F_CUTY, F_CUTZ = 16, 32, 64

@@ -49,6 +49,11 @@ def cases_small():
         "mixed_bodies_48", W.uniform_faces(48), W.uniform_faces(48), W.uniform_faces(48),
         [W.sphere((0.3, 0.3, 0.5), 0.15), W.plate((0.7, 0.6, 0.5), 0.2, 0.5, 20, 50, 0.03, 0.4)])
     out["mixed_bodies_48"].f = W.noise_rhs(48 ** 3, 6)
+    # every dimension odd: level 0 has a padding slot per row of each colour
+    # and the hierarchy is that level alone
+    out["odd_fine"] = W.Problem("odd_fine", W.uniform_faces(35), W.uniform_faces(21, 0.6), W.uniform_faces(13, 0.4),
+                                [W.sphere((0.45, 0.3, 0.2), 0.12, freq=6)])
+    out["odd_fine"].f = W.noise_rhs(35 * 21 * 13, 7)
     out["empty_box"] = W.Problem("empty_box", W.uniform_faces(16), W.uniform_faces(16), W.uniform_faces(16), [])
     out["empty_box"].f = W.manufactured_rhs(out["empty_box"].xf, out["empty_box"].yf, out["empty_box"].zf)
     return out
