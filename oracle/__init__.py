@@ -7,10 +7,14 @@ and in the plain numpy below).
 
 Pins (tests/test_oracle_*.py) tie it to the paper and to mathematics:
 closed-form eigenvector solutions, direct sparse solves of an independently
-assembled matrix, exact rational ray parity, trilinear reproduction and
-flat-wall equivalence.  The degenerate-stencil fallback and the membrane
-ghost rows away from a flat sheet are "parity unpinned" (only their counts
-and structural properties are checked).
+assembled matrix, exact rational ray parity, the closest point against an
+independent construction, trilinear reproduction by the ghost rows of closed
+bodies and of a cambered membrane (whose columns include other membrane
+ghost unknowns) with the mirror geometry of their image points, flat-wall
+and flat-membrane equivalence.  The degenerate-stencil fallback is pinned
+by its invariants only: it reproduces constants, reads face neighbours on
+the ghost's own side, and misses a linear field by at most its gradient
+times the farthest neighbour.
 """
 from __future__ import annotations
 

@@ -196,6 +196,111 @@ def test_p4_trilinear_reproduction(case):
         assert np.abs(lhs - rhs).max() < 1e-11
 
 
+def _row_positions(p, S):
+    """Cell-centre coordinates of every ghost row's own cell and a function
+    giving the position of a stencil column (a cell, or a membrane ghost
+    unknown, which sits at its cell's centre)."""
+    cs = [refpy.centres(p.xf), refpy.centres(p.yf), refpy.centres(p.zf)]
+    nx, ny = len(cs[0]), len(cs[1])
+    N = len(S.flags)
+
+    def pos(cell):
+        return np.stack([cs[0][cell % nx], cs[1][(cell // nx) % ny], cs[2][cell // (nx * ny)]], -1)
+
+    def col_pos(col):
+        cell = np.where(col >= 0, col, 0)
+        if S.st.nm:
+            cell = np.where(col >= N, S.st.mcell[np.clip(col - N, 0, S.st.nm - 1)], cell)
+        return pos(cell)
+    return cs, pos(S.st.row_cell), col_pos
+
+
+@pytest.mark.parametrize("n", [64, 96])
+def test_p4_membrane_rows_trilinear_reproduction_and_geometry(n):
+    """Membrane ghost rows of a cambered plate (columns include the ghost
+    unknowns of other membrane cells): for any trilinear phi,
+    sum w_k phi(x_k) + beta_BI dphi/dn(BI) = phi(IP); and IP is G mirrored
+    through BI, the stored distance is |G - BI|, dl = 2 |G - BI|, n is a unit
+    vector along BI - G."""
+    p = W.membrane_case(n, nc=40, ns=120)
+    S = setup_problem(p.xf, p.yf, p.zf, p.bodies)
+    st = S.st
+    assert st.ng == 0 and st.nm > 1000
+    cs, G, col_pos = _row_positions(p, S)
+    BI, IP, nrm = st.geo[:, 0:3], st.geo[:, 3:6], st.geo[:, 6:9]
+    dl, dist = st.geo[:, 9], st.geo[:, 11]
+    assert np.abs(IP - (2 * BI - G)).max() < 1e-15
+    assert np.abs(dist - np.linalg.norm(G - BI, axis=1)).max() < 1e-15
+    assert np.abs(dl - 2 * dist).max() < 1e-15
+    assert np.abs(np.linalg.norm(nrm, axis=1) - 1).max() < 1e-14
+    v = BI - G
+    assert np.abs(np.cross(nrm, v)).max() < 1e-15 and (np.sum(nrm * v, 1) > 0).all()
+    ok = np.nonzero((st.rfl & 1) == 0)[0]
+    assert len(ok) > 0.95 * len(st.rfl)
+    N = len(S.flags)
+    assert (st.col[ok] >= N).any(1).sum() > 0.5 * len(ok)  # rows that read other membrane unknowns
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        c = rng.uniform(-1, 1, 8)
+
+        def phi(x):
+            X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+            return c[0] + c[1] * X + c[2] * Y + c[3] * Z + c[4] * X * Y + c[5] * Y * Z + c[6] * X * Z + c[7] * X * Y * Z
+
+        def grad(x):
+            X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+            return np.stack([c[1] + c[4] * Y + c[6] * Z + c[7] * Y * Z, c[2] + c[4] * X + c[5] * Z + c[7] * X * Z,
+                             c[3] + c[5] * Y + c[6] * X + c[7] * X * Y], -1)
+        col, w = st.col[ok], st.w[ok]
+        lhs = np.sum(np.where(col >= 0, w * phi(col_pos(col)), 0.0), 1)
+        lhs += st.geo[ok, 10] * np.sum(grad(BI[ok]) * nrm[ok], 1)
+        ip = IP[ok].copy()
+        for d in range(3):
+            ip[:, d] = np.clip(ip[:, d], cs[d][0], cs[d][-1])
+        assert np.abs(lhs - phi(ip)).max() < 1e-11
+
+
+@pytest.mark.parametrize("case", ["c2_64", "membrane_64"])
+def test_p4_fallback_rows_invariants(case):
+    """Rows whose trilinear box is degenerate fall back to first order: they
+    reproduce constants exactly (weights sum to one, no boundary term), use
+    only face neighbours on the ghost's own side (fluid cells for a closed
+    ghost, cells across a cut link for a membrane ghost), and miss a linear
+    field by no more than its gradient times the farthest neighbour."""
+    p = W.sphere_ellipsoid_case(64) if case == "c2_64" else W.membrane_case(64, nc=40, ns=120)
+    S = setup_problem(p.xf, p.yf, p.zf, p.bodies)
+    st = S.st
+    fb = np.nonzero(st.rfl & 1)[0]
+    assert len(fb) > 0
+    cs, G, col_pos = _row_positions(p, S)
+    nx, ny, nz = len(cs[0]), len(cs[1]), len(cs[2])
+    cut = [oracle.F_CUTX, oracle.F_CUTY, oracle.F_CUTZ]
+    for r in fb:
+        col, w = st.col[r], st.w[r]
+        used = col >= 0
+        k = int(used.sum())
+        assert k >= 1 and np.allclose(w[used], 1.0 / k, rtol=0, atol=1e-16) and np.all(w[~used] == 0)
+        assert abs(w.sum() - 1.0) < 1e-15 and st.dlb[r] == 0.0
+        gc = int(st.row_cell[r])
+        gi, gj, gk = gc % nx, (gc // nx) % ny, gc // (nx * ny)
+        for q in col[used]:
+            q = int(q)
+            qi, qj, qk = q % nx, (q // nx) % ny, q // (nx * ny)
+            dv = np.array([qi - gi, qj - gj, qk - gk])
+            assert np.abs(dv).sum() == 1  # a face neighbour
+            if r < st.ng:
+                assert not (S.flags[q] & oracle.F_SOLID)
+            else:
+                d = int(np.nonzero(dv)[0][0])
+                lo = gc if dv[d] > 0 else q  # the link's lower cell carries its cut bit
+                assert S.flags[lo] & cut[d]
+    g = np.array([0.7, -0.4, 0.25])
+    col = st.col[fb]
+    lin = np.sum(np.where(col >= 0, st.w[fb] * (col_pos(col) @ g), 0.0), 1)
+    hmax = np.linalg.norm(col_pos(col) - G[fb][:, None, :], axis=2).max(1)
+    assert np.all(np.abs(lin - G[fb] @ g) <= np.linalg.norm(g) * hmax * (1 + 1e-12))
+
+
 # ---------------------------------------------------------------- P5
 def test_p5_flat_wall_equals_truncated_box():
     """A slab whose surface lies on the face plane z = 24/32 reproduces the
