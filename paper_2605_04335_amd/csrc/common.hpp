@@ -142,6 +142,10 @@ HostGrid read_grid(const ibm_grid *g);
 
 constexpr uint8_t F_SOLID = IBM_F_SOLID, F_GHOST = IBM_F_GHOST, F_MGHOST = IBM_F_MGHOST, F_PIN = IBM_F_PIN,
                   F_CUTX = IBM_F_CUTX;
+// bit 7 of the solver's own level-0 mask (never of the classification
+// output): the slot is read by a ghost row or a membrane row, so it must be
+// zero when those rows run after a V-cycle's first (red) half-sweep
+constexpr uint8_t F_RD = 0x80;
 
 }  // namespace ibm
 

@@ -657,8 +657,13 @@ __global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T 
 
 // First level-0 half-sweep of a V-cycle, from a zero iterate: every regular
 // cell of colour c gets -b/diag (its neighbours are zero), every other slot
-// of both colours gets 0.  32-bit offsets from the tile's first plane,
-// non-temporal stores (as k0_sweep).
+// of colour c gets 0.  Of the other colour only the slots that something
+// reads before that colour's own half-sweep are zeroed: solid and padding
+// slots, membrane-adjacent cells, and the slots ghost and membrane rows read
+// (F_RD); the rest is overwritten by that half-sweep unread, so its stale
+// values never count (writing all of it cost a quarter of this kernel's
+// bytes).  32-bit offsets from the tile's first plane, non-temporal stores
+// (as k0_sweep).
 template <class T>
 __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_s, T *__restrict__ xc,
                                                      T *__restrict__ xo, const T *__restrict__ bc,
@@ -671,7 +676,7 @@ __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_
     const uint32_t pl = (uint32_t)(L.H * L.ny);
     const long long base = (long long)pl * k0;
     const T *bp = bc + base;
-    const uint8_t *fb = fc + base;
+    const uint8_t *fb = fc + base, *fo = fc + ((c ? -1 : 1) * L.Nh) + base;
     T *xw = xc + base, *xz = xo + base;
     const uint32_t col = (uint32_t)(h + L.H * j);
     const double snk = pin_s >= 0 ? sink[0] : 0.0;
@@ -680,13 +685,14 @@ __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_
     constexpr int UZ = 4;
     for (int kb = k0; kb < k1; kb += UZ) {
         double bv[UZ], zp[UZ], zm[UZ];
-        uint8_t fv[UZ];
+        uint8_t fv[UZ], fz[UZ];
 #pragma unroll
         for (int u = 0; u < UZ; ++u) {
             const int k = min(kb + u, k1 - 1);
             const uint32_t s = col + pl * (uint32_t)(k - k0);
             bv[u] = ldu(bp, s);
             fv[u] = ldu(fb, s);
+            fz[u] = ldu(fo, s);
             zp[u] = L.cp[2][k];
             zm[u] = L.cm[2][k];
         }
@@ -700,7 +706,7 @@ __global__ void __launch_bounds__(TPB) k0_sweep_zero(Lv L, Geo G, long long pin_
             double b0 = bv[u];
             if ((long long)s == pin_rel) b0 -= snk;
             st_nt(xw + s, (T)((fv[u] & (F_SOLID | F_MGHOST)) ? 0.0 : -b0 / dg));
-            st_nt(xz + s, (T)0.0);
+            if (fz[u] & (F_SOLID | F_MGHOST | F_RD)) st_nt(xz + s, (T)0.0);
         }
     }
 }

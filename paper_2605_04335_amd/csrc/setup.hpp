@@ -91,6 +91,18 @@ __global__ void __launch_bounds__(TPB) k_setup_membrane(SlotMap m, int nz, long 
     }
 }
 
+// mark (F_RD) the level-0 slots that the given row columns read (ghost
+// stencils: 8 per row; membrane cells: 6 neighbours); several threads may set
+// the bit of one slot, all writing the same byte
+__global__ void __launch_bounds__(TPB) k_mark_read(long long n, const int32_t *__restrict__ cols, long long N2,
+                                                   uint8_t *__restrict__ spl)
+{
+    for (long long q = blockIdx.x * (long long)TPB + threadIdx.x; q < n; q += (long long)gridDim.x * TPB) {
+        const int32_t v = cols[q];
+        if (v >= 0 && v < N2) spl[v] = (uint8_t)(spl[v] | F_RD);
+    }
+}
+
 // volume of the fluid cells (per-block partial sums)
 __global__ void __launch_bounds__(TPB) k_fluid_volume(Lv L, Walk W, double *part)
 {

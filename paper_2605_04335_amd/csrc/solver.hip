@@ -762,6 +762,10 @@ void setup_geometry(poisson_ctx &c, const uint8_t *flags, const ibm_stencils *st
     if (nm)
         k_setup_membrane<<<blocks(nm), TPB, 0, s>>>(sm, nz, nm, st->cell.p + c.ng, flags, c.mslot.p, c.mcol.p,
                                                     c.mcolor.p, c.serr.p);
+    // the slots those rows read (the first half-sweep of a V-cycle zeroes
+    // these, not every black slot)
+    if (R) k_mark_read<<<blocks(8 * R), TPB, 0, s>>>(8 * R, c.rcol.p, c.N2, Z.m.p);
+    if (nm) k_mark_read<<<blocks(6 * nm), TPB, 0, s>>>(6 * nm, c.mcol.p, c.N2, Z.m.p);
     // fluid volume, then the coarse masks level by level with their active volumes
     k_fluid_volume<<<Z.walk.nb, TPB, 0, s>>>(Z.lv, Z.walk, c.part.p);
     k_fin<<<1, 1024, 0, s>>>(c.part.p, PSTRIDE, Z.walk.nb, FIN_SUM, 0, 0.0, c.ssum.p);
