@@ -599,6 +599,10 @@ __global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T 
                                                 const uint8_t *__restrict__ fc, const double *__restrict__ sink, int c)
 {
     constexpr int UP = SweepPlanes<T>::n;
+    // FP32: the x and y neighbours of plane k+1 are loaded with plane k+1's
+    // centre, one step ahead of their use, so a step's loads all fall in the
+    // planes being fetched then (4% faster at 512^3; FP64 gained nothing)
+    constexpr bool AHEAD = sizeof(T) == 4;
     int h, j, k0, k1;
     if (!geo_tile(G, h, j, k0, k1)) return;
     const Col0 q = col0(L, c, h, j);
@@ -615,18 +619,33 @@ __global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T 
     // centres of planes k-1 and k (zero coefficient outside the grid)
     double cprev = k0 > 0 ? (double)ldu(xb, col + pl * (uint32_t)(k0 - 1 - kb)) : 0.0;
     double ccur = ldu(xb, col + pl * (uint32_t)(k0 - kb));
+    // x and y neighbours of the next plane to update (used only ahead of time)
+    double xsa = 0.0, ypa = 0.0, yma = 0.0;
+    if constexpr (AHEAD) {
+        const uint32_t s = col + pl * (uint32_t)(k0 - kb);
+        xsa = ldu(xb, s + (uint32_t)((k0 & 1) ? ox1 : ox0));
+        ypa = ldu(xb, s + (uint32_t)oyp);
+        yma = ldu(xb, s + (uint32_t)oym);
+    }
     for (int ks = k0; ks < k1; ks += UP) {
         double cn[UP], xs[UP], yp[UP], ym[UP], bb[UP], czp[UP], czm[UP];
         uint8_t fl[UP];
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             const int k = min(ks + u, k1 - 1);
-            const uint32_t s = col + pl * (uint32_t)(k - kb);
+            const int kn = min(k + 1, L.nz - 1);
+            const uint32_t s = col + pl * (uint32_t)(k - kb), sn = col + pl * (uint32_t)(kn - kb);
             const bool t = k & 1;
-            cn[u] = ldu(xb, col + pl * (uint32_t)(min(k + 1, L.nz - 1) - kb));  // centre of plane k+1
-            xs[u] = ldu(xb, s + (uint32_t)(t ? ox1 : ox0));
-            yp[u] = ldu(xb, s + (uint32_t)oyp);
-            ym[u] = ldu(xb, s + (uint32_t)oym);
+            cn[u] = ldu(xb, sn);  // centre of plane k+1
+            if constexpr (AHEAD) {  // plane k+1's neighbours
+                xs[u] = ldu(xb, sn + (uint32_t)((kn & 1) ? ox1 : ox0));
+                yp[u] = ldu(xb, sn + (uint32_t)oyp);
+                ym[u] = ldu(xb, sn + (uint32_t)oym);
+            } else {  // plane k's
+                xs[u] = ldu(xb, s + (uint32_t)(t ? ox1 : ox0));
+                yp[u] = ldu(xb, s + (uint32_t)oyp);
+                ym[u] = ldu(xb, s + (uint32_t)oym);
+            }
             fl[u] = ldu(fb, s);
             bb[u] = ldu(bp, s);
             czp[u] = L.cp[2][k];  // zero at the walls
@@ -637,14 +656,17 @@ __global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T 
             const int k = ks + u;
             const double cc = u == 0 ? ccur : cn[u - 1];
             const double cm = u == 0 ? cprev : (u == 1 ? ccur : cn[u - 2]);
+            const double xk = !AHEAD ? xs[u] : (u == 0 ? xsa : xs[u - 1]);
+            const double ypk = !AHEAD ? yp[u] : (u == 0 ? ypa : yp[u - 1]);
+            const double ymk = !AHEAD ? ym[u] : (u == 0 ? yma : ym[u - 1]);
             if (k >= k1) continue;
             const uint32_t s = col + pl * (uint32_t)(k - kb);
             const bool t = k & 1;
             const double cpx = t ? q.cpx[1] : q.cpx[0], cmx = t ? q.cmx[1] : q.cmx[0];
             const int oxp = t ? q.oxp[1] : q.oxp[0], oxm = t ? q.oxm[1] : q.oxm[0];
-            const double xpv = oxp == 0 ? cc : xs[u], xmv = oxm == 0 ? cc : xs[u];
+            const double xpv = oxp == 0 ? cc : xk, xmv = oxm == 0 ? cc : xk;
             const double dg = cpx + cmx + q.cpy + q.cmy + czp[u] + czm[u];
-            const double nb = cpx * xpv + cmx * xmv + q.cpy * yp[u] + q.cmy * ym[u] + czp[u] * cn[u] + czm[u] * cm;
+            const double nb = cpx * xpv + cmx * xmv + q.cpy * ypk + q.cmy * ymk + czp[u] * cn[u] + czm[u] * cm;
             if (fl[u] & (F_SOLID | F_MGHOST)) continue;
             double b0 = bb[u];
             if ((long long)s == pin_rel) b0 -= sink[0];
@@ -652,6 +674,11 @@ __global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T 
         }
         cprev = cn[UP - 2];
         ccur = cn[UP - 1];
+        if constexpr (AHEAD) {
+            xsa = xs[UP - 1];
+            ypa = yp[UP - 1];
+            yma = ym[UP - 1];
+        }
     }
 }
 
