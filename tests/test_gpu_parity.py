@@ -188,7 +188,7 @@ def test_fp64_solve_config_tolerance_c1(torch_cuda):
     assert rel(x.cpu().numpy(), xo) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["c1", "c2_64", "membrane_64", "mixed_bodies_48"])
+@pytest.mark.parametrize("name", ["c1", "c2_64", "membrane_64", "mixed_bodies_48", "odd_fine", "box_odd"])
 def test_mixed_solve_within_1e8(torch_cuda, name):
     torch = torch_cuda
     p = CASES[name]
@@ -312,7 +312,7 @@ def test_caller_owned_workspace(torch_cuda, precision):
 
 
 # ---------------------------------------------------------------- SRJ preconditioner
-@pytest.mark.parametrize("name", ["c1", "membrane_64", "mixed_bodies_48", "box_odd"])
+@pytest.mark.parametrize("name", ["c1", "membrane_64", "mixed_bodies_48", "box_odd", "odd_fine"])
 def test_srj_precond_matches_oracle(torch_cuda, name):
     torch = torch_cuda
     p = CASES[name]
