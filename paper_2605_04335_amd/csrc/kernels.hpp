@@ -771,9 +771,12 @@ __device__ __forceinline__ bool apply_out(uint8_t f, double xv, double nsum, dou
 // neighbour and the two y neighbours.  As in the half-sweep, every load of a
 // step is issued unconditionally before any arithmetic (a wall reads the
 // cell's partner slot, with a zero coefficient), and addresses are 32-bit
-// offsets from block-uniform bases; this keeps the kernel at about 90 VGPRs
-// in FP64 (5 waves per SIMD) where indexing each neighbour with 64-bit
-// addresses took over 130 (3 waves).  Two planes per step.
+// offsets from block-uniform bases; this keeps the kernel at about 100
+// VGPRs in FP64 (4-5 waves per SIMD) where indexing each neighbour with
+// 64-bit addresses took over 130 (3 waves).  Two planes per step.  The outer x and
+// the y neighbours of plane k+1 are loaded with its centres, one step ahead
+// of their use, so that a step's loads fall in the plane being fetched
+// (equal time in FP64, 2% faster in FP32, fewer bytes from HBM in both).
 template <class T, int MODE, bool RES, int ND>
 __global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, const T *__restrict__ x, T *__restrict__ y,
                                                  const T *__restrict__ b, const double *__restrict__ sink,
@@ -816,11 +819,23 @@ __global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, con
         auto zo = [&](int kk) { return pl * (uint32_t)(kk - kb); };
         // both colours' centres in planes k-1 and k (below the bottom wall:
         // plane k itself)
-        double cm0[2], cc0[2];
+        double cm0[2], cc0[2], xa[2], ypa[2], yma[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             cm0[c] = ldu(xb[c], col + zo(max(k0 - 1, 0)));
             cc0[c] = ldu(xb[c], col + zo(k0));
+        }
+        {
+            // x and y neighbours of plane k0 (later planes' come one step ahead)
+            const uint32_t s = col + zo(k0);
+            const int p0 = (j ^ k0) & 1;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int e = c ? 1 - p0 : p0;
+                xa[c] = ldu(xb[1 - c], s + (uint32_t)oxe[e]);
+                ypa[c] = ldu(xb[1 - c], s + (uint32_t)oyp);
+                yma[c] = ldu(xb[1 - c], s + (uint32_t)oym);
+            }
         }
         for (int ks = k0; ks < k1; ks += UA) {
             double cn[UA][2], xo[UA][2], yp[UA][2], ym[UA][2], uv[UA][2], wv[UA][2], bv[UA][2], czp[UA], czm[UA];
@@ -828,15 +843,16 @@ __global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, con
 #pragma unroll
             for (int u = 0; u < UA; ++u) {
                 const int k = min(ks + u, k1 - 1);
-                const uint32_t s = col + zo(k);
-                const int p0 = (j ^ k) & 1;  // colour 0 sits at i = 2h + p0, colour 1 at 2h + 1 - p0
+                const int kn = min(k + 1, L.nz - 1);
+                const uint32_t s = col + zo(k), sn = col + zo(kn);
+                const int pn = (j ^ kn) & 1;
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    const int e = c ? 1 - p0 : p0;
-                    cn[u][c] = ldu(xb[c], col + zo(min(k + 1, L.nz - 1)));  // centre of plane k+1
-                    xo[u][c] = ldu(xb[1 - c], s + (uint32_t)oxe[e]);
-                    yp[u][c] = ldu(xb[1 - c], s + (uint32_t)oyp);
-                    ym[u][c] = ldu(xb[1 - c], s + (uint32_t)oym);
+                    const int en = c ? 1 - pn : pn;
+                    cn[u][c] = ldu(xb[c], sn);  // centre of plane k+1
+                    xo[u][c] = ldu(xb[1 - c], sn + (uint32_t)oxe[en]);  // plane k+1's neighbours
+                    yp[u][c] = ldu(xb[1 - c], sn + (uint32_t)oyp);
+                    ym[u][c] = ldu(xb[1 - c], sn + (uint32_t)oym);
                     fv[u][c] = ldu(fb[c], s);
                     uv[u][c] = ND >= 1 ? (double)ldu(ub[c], s) : 0.0;
                     wv[u][c] = ND >= 2 ? (double)ldu(vb[c], s) : 0.0;
@@ -859,8 +875,10 @@ __global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, con
                     const double pc = u == 0 ? cc0[o] : cn[u - 1][o];
                     const double pm = u == 0 ? cm0[o] : (u == 1 ? cc0[o] : cn[u - 2][o]);
                     const double pp = cn[u][o];
-                    const double xpv = ope[e] == 0 ? pc : xo[u][c], xmv = ome[e] == 0 ? pc : xo[u][c];
-                    const double nsum = cpe[e] * xpv + cme[e] * xmv + cpy * yp[u][c] + cmy * ym[u][c] + czp[u] * pp +
+                    const double xk = u == 0 ? xa[c] : xo[u - 1][c];
+                    const double ypk = u == 0 ? ypa[c] : yp[u - 1][c], ymk = u == 0 ? yma[c] : ym[u - 1][c];
+                    const double xpv = ope[e] == 0 ? pc : xk, xmv = ome[e] == 0 ? pc : xk;
+                    const double nsum = cpe[e] * xpv + cme[e] * xmv + cpy * ypk + cmy * ymk + czp[u] * pp +
                                         czm[u] * pm;
                     const double dg = cpe[e] + cme[e] + cpy + cmy + czp[u] + czm[u];
                     const double xv = u == 0 ? cc0[c] : cn[u - 1][c];
@@ -877,6 +895,9 @@ __global__ void __launch_bounds__(TPB) k0_apply2(Lv L, Geo G, long long pin, con
             for (int c = 0; c < 2; ++c) {
                 cm0[c] = cn[UA - 2][c];
                 cc0[c] = cn[UA - 1][c];
+                xa[c] = xo[UA - 1][c];
+                ypa[c] = yp[UA - 1][c];
+                yma[c] = ym[UA - 1][c];
             }
         }
     }
