@@ -188,6 +188,8 @@ int32_t ibm_classify_noalloc(const ibm_grid *grid, const ibm_body *bodies, int32
  * solve with partial pivoting per ghost (the batched inversions of Sec. 2.5).
  *   flags_dev: the output of ibm_classify; *out receives a library-owned
  *   table (free with ibm_stencils_free).  Synchronises to size the table.
+ * Columns are int32, so cells plus membrane ghost unknowns must stay below
+ * 2^31 (IBM_EINVAL otherwise).
  */
 int32_t ibm_build_ghost_stencils(const ibm_grid *grid, const ibm_body *bodies, int32_t n_body,
                                  const uint8_t *flags_dev, ibm_stencils **out, void *stream);
@@ -231,6 +233,9 @@ void ibm_stencils_free(ibm_stencils *s);
  * multigrid hierarchy and the Krylov work vectors, all in library-owned
  * device memory.  *workspace_bytes (may be NULL) receives that footprint.
  * flags_dev and the stencil table are not referenced after the call.
+ * IBM_EINVAL for bad options, a table of another grid, or more than 2^31
+ * unknowns (cell slots, each x-row padded to even length, plus membrane
+ * ghost unknowns: the row columns are int32).
  */
 int32_t poisson_setup(const ibm_grid *grid, const uint8_t *flags_dev, const ibm_stencils *st,
                       const poisson_opts *opts, size_t *workspace_bytes, poisson_ctx **out);

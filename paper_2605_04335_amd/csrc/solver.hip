@@ -718,6 +718,8 @@ void setup_geometry(poisson_ctx &c, const uint8_t *flags, const ibm_stencils *st
     const HostGrid &g = c.g;
     for (int d = 0; d < 3; ++d) IBM_REQUIRE(g.n[d] == st->n[d], IBM_EINVAL, "stencil table of another grid");
     IBM_REQUIRE(st->pin >= 0 && st->pin < c.N, IBM_EGEOM, "no fluid cell to pin");
+    // row columns are int32 slots: the cell slots (with row padding), then the membrane ghost unknowns
+    IBM_REQUIRE(c.N2 + st->nm < (1LL << 31), IBM_EINVAL, "more than 2^31 unknowns with padding and membrane ghosts");
     hipStream_t s = c.cs;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int nl = (int)c.lv.size();

@@ -451,6 +451,8 @@ void build_stencils(const ibm_grid *grid, const ibm_body *bodies, int n_body, co
         DBuf<int32_t> gl, ml;
         S->ng = compact_cells(flags, N, F_GHOST, gl, s);
         S->nm = compact_cells(flags, N, F_MGHOST, ml, s);
+        // stencil columns are int32: grid unknowns, then membrane ghost unknowns
+        IBM_REQUIRE(N + S->nm < ((int64_t)1 << 31), IBM_EINVAL, "more than 2^31 unknowns with the membrane ghosts");
         const int64_t rows = S->ng + S->nm;
         S->cell.alloc(std::max<int64_t>(rows, 1));
         if (S->ng) IBM_HIP(hipMemcpyAsync(S->cell.p, gl.p, S->ng * 4, hipMemcpyDeviceToDevice, s));
