@@ -54,6 +54,17 @@ def cases_small():
     out["odd_fine"] = W.Problem("odd_fine", W.uniform_faces(35), W.uniform_faces(21, 0.6), W.uniform_faces(13, 0.4),
                                 [W.sphere((0.45, 0.3, 0.2), 0.12, freq=6)])
     out["odd_fine"].f = W.noise_rhs(35 * 21 * 13, 7)
+    # a sphere cut by the x = 0 wall: ghost stencils whose image-point boxes
+    # are clamped at the wall and take other ghost cells as nodes
+    out["wall_sphere_40"] = W.Problem("wall_sphere_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
+                                      [W.sphere((0.08, 0.5, 0.45), 0.2, freq=8)])
+    out["wall_sphere_40"].f = W.noise_rhs(40 ** 3, 8)
+    # two spheres 1.4 cells apart on a stretched grid: ghosts of one body
+    # whose boxes reach the other's cells
+    sf = W.stretched_faces(48)[0]
+    out["near_pair_48"] = W.Problem("near_pair_48", sf, sf, sf, [W.sphere((0.35, 0.5, 0.5), 0.12, freq=8),
+                                                                 W.sphere((0.62, 0.5, 0.5), 0.12, freq=8)])
+    out["near_pair_48"].f = W.noise_rhs(48 ** 3, 9)
     out["empty_box"] = W.Problem("empty_box", W.uniform_faces(16), W.uniform_faces(16), W.uniform_faces(16), [])
     out["empty_box"].f = W.manufactured_rhs(out["empty_box"].xf, out["empty_box"].yf, out["empty_box"].zf)
     return out
@@ -188,7 +199,8 @@ def test_fp64_solve_config_tolerance_c1(torch_cuda):
     assert rel(x.cpu().numpy(), xo) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["c1", "c2_64", "membrane_64", "mixed_bodies_48", "odd_fine", "box_odd"])
+@pytest.mark.parametrize("name", ["c1", "c2_64", "membrane_64", "mixed_bodies_48", "odd_fine", "box_odd",
+                                  "wall_sphere_40", "near_pair_48"])
 def test_mixed_solve_within_1e8(torch_cuda, name):
     torch = torch_cuda
     p = CASES[name]
@@ -312,7 +324,7 @@ def test_caller_owned_workspace(torch_cuda, precision):
 
 
 # ---------------------------------------------------------------- SRJ preconditioner
-@pytest.mark.parametrize("name", ["c1", "membrane_64", "mixed_bodies_48", "box_odd", "odd_fine"])
+@pytest.mark.parametrize("name", ["c1", "membrane_64", "mixed_bodies_48", "box_odd", "odd_fine", "near_pair_48"])
 def test_srj_precond_matches_oracle(torch_cuda, name):
     torch = torch_cuda
     p = CASES[name]
