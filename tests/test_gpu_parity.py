@@ -65,6 +65,16 @@ def cases_small():
     out["near_pair_48"] = W.Problem("near_pair_48", sf, sf, sf, [W.sphere((0.35, 0.5, 0.5), 0.12, freq=8),
                                                                  W.sphere((0.62, 0.5, 0.5), 0.12, freq=8)])
     out["near_pair_48"].f = W.noise_rhs(48 ** 3, 9)
+    # a membrane through both y walls (cut links in the boundary cells; the
+    # fluid stays connected around its edges)
+    out["wall_plate_40"] = W.Problem("wall_plate_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
+                                     [W.plate((0.5, 0.5, 0.47), 0.3, 1.3, 12, 52, 0.03, 0.4)])
+    out["wall_plate_40"].f = W.noise_rhs(40 ** 3, 10)
+    # a closed body under half a cell thick: every solid cell is a ghost
+    out["thin_ellipsoid_40"] = W.Problem(
+        "thin_ellipsoid_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
+        [W.ellipsoid((0.5, 0.5, 0.5123), (0.2, 0.15, 0.011), W.rotation_zyx(0.3, 0.0, 0.0), freq=8)])
+    out["thin_ellipsoid_40"].f = W.noise_rhs(40 ** 3, 11)
     out["empty_box"] = W.Problem("empty_box", W.uniform_faces(16), W.uniform_faces(16), W.uniform_faces(16), [])
     out["empty_box"].f = W.manufactured_rhs(out["empty_box"].xf, out["empty_box"].yf, out["empty_box"].zf)
     return out
@@ -200,7 +210,7 @@ def test_fp64_solve_config_tolerance_c1(torch_cuda):
 
 
 @pytest.mark.parametrize("name", ["c1", "c2_64", "membrane_64", "mixed_bodies_48", "odd_fine", "box_odd",
-                                  "wall_sphere_40", "near_pair_48"])
+                                  "wall_sphere_40", "near_pair_48", "wall_plate_40", "thin_ellipsoid_40"])
 def test_mixed_solve_within_1e8(torch_cuda, name):
     torch = torch_cuda
     p = CASES[name]
@@ -324,7 +334,8 @@ def test_caller_owned_workspace(torch_cuda, precision):
 
 
 # ---------------------------------------------------------------- SRJ preconditioner
-@pytest.mark.parametrize("name", ["c1", "membrane_64", "mixed_bodies_48", "box_odd", "odd_fine", "near_pair_48"])
+@pytest.mark.parametrize("name", ["c1", "membrane_64", "mixed_bodies_48", "box_odd", "odd_fine", "near_pair_48",
+                                  "wall_plate_40"])
 def test_srj_precond_matches_oracle(torch_cuda, name):
     torch = torch_cuda
     p = CASES[name]
