@@ -41,6 +41,13 @@ CASES = {
                                          [W.sphere((0.33, 0.5, 0.5), 0.17, freq=8),
                                           W.plate((0.72, 0.5, 0.5), 0.2, 0.4, 10, 20, 0.04, 0.3)]),
     "flapping_48": lambda: W.flapping_case(48, 200, rhs=False),
+    # a sphere cut by the x = 0 wall, an ellipsoid under half a cell thick and
+    # a membrane through both y walls
+    "walls_thin_40": lambda: W.Problem(
+        "walls_thin_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
+        [W.sphere((0.08, 0.5, 0.45), 0.2, freq=8),
+         W.ellipsoid((0.6, 0.5, 0.5123), (0.2, 0.15, 0.011), W.rotation_zyx(0.3, 0.0, 0.0), freq=8),
+         W.plate((0.65, 0.5, 0.27), 0.3, 1.3, 12, 52, 0.03, 0.4)]),
 }
 
 

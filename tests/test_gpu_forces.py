@@ -51,6 +51,22 @@ def test_forces_match_oracle(P, n):
     assert np.allclose(F[:nv0].sum(0), Fo[:nv0].sum(0), rtol=1e-12, atol=1e-18)
 
 
+def test_forces_walls_and_thin_body(P):
+    """Probes near the domain walls and on a body under half a cell thick:
+    a sphere cut by the x = 0 wall, a thin ellipsoid, a membrane through both
+    y walls."""
+    import torch
+    p = W.Problem("walls_thin_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
+                  [W.sphere((0.08, 0.5, 0.45), 0.2, freq=8),
+                   W.ellipsoid((0.6, 0.5, 0.5123), (0.2, 0.15, 0.011), W.rotation_zyx(0.3, 0.0, 0.0), freq=8),
+                   W.plate((0.65, 0.5, 0.27), 0.3, 1.3, 12, 52, 0.03, 0.4)])
+    p.f = W.noise_rhs(40 ** 3, 12)
+    flags, st, sol, _ = P.setup(p.xf, p.yf, p.zf, p.bodies, tol=1e-10)
+    x, s = sol.solve(torch.from_numpy(p.f).cuda())
+    assert s.status == 0
+    check(P, p, x, flags)
+
+
 def test_forces_linear_field_closed_form(P):
     """The closed-form case of the oracle's pins, on the GPU: a cube in
     p = a.x on a uniform grid gets -(a L^3 + 2 d L^2 a)."""
