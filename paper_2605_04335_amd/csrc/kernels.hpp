@@ -290,6 +290,7 @@ struct Sp {
     const int32_t *mslot;  // [nm] slots of the membrane-adjacent cells
     const int32_t *mcol;   // [nm*6] -x,+x,-y,+y,-z,+z neighbour unknowns (-1: wall)
     const int32_t *mcolor; // [nm] colour of each membrane cell (0/1)
+    const int32_t *rmrow;  // [nrows*8] membrane cell behind each stencil column (-1: none)
 };
 
 __device__ __forceinline__ long long ghost_unknown(const Sp &S, int r)
@@ -1020,7 +1021,7 @@ __device__ __forceinline__ double stencil_sum(const T *x, long long fallback, co
 // a cut link the neighbour's ghost unknown is eliminated, i.e. replaced by
 // the current value of its stencil, sum w x - b/sG
 // All cells of the colour read the same iterate (their eliminated stencils
-// may reach each other): new values go to tmp, k0_mscat writes them.
+// may reach each other): new values go to tmp, k0_mscat_gjac writes them.
 // The loads go out in batches (the row's indices; the direct neighbours and
 // the stencils of its first two cut links; the stencil values), so a row
 // waits on three dependent steps rather than on one per neighbour; a third
@@ -1085,20 +1086,51 @@ __global__ void __launch_bounds__(TPB) k0_msweep(Lv L, Sp S, const T *x, const T
     }
 }
 
+// After the membrane cells of one colour: their new values (staged in mtmp
+// by k0_msweep) are written to x, and in the same launch one Jacobi update
+// of every ghost unknown is staged in gtmp (k0_gscat writes it).  The ghost
+// rows must see the colour's new membrane values, which other threads of
+// this launch are writing: a stencil column that is a membrane cell of the
+// colour (rmrow) takes its value from mtmp, rounded to T as the store
+// rounds it, so the result is that of scattering first.  Sum in column
+// order (as ghost_sum).
 template <class T>
-__global__ void __launch_bounds__(TPB) k0_mscat(Sp S, T *x, int color, const double *tmp)
+__global__ void __launch_bounds__(TPB) k0_mscat_gjac(Sp S, T *x, const T *b, int color, const double *mtmp,
+                                                     double *gtmp)
 {
-    for (int m = blockIdx.x * TPB + threadIdx.x; m < S.nm; m += gridDim.x * TPB)
-        if (S.mcolor[m] == color) st(x, S.mslot[m], tmp[m]);
-}
-
-// Jacobi on every ghost unknown, staged so that all rows read the same iterate
-template <class T>
-__global__ void __launch_bounds__(TPB) k0_gjac(Sp S, const T *x, const T *b, double *tmp)
-{
-    for (int r = blockIdx.x * TPB + threadIdx.x; r < S.nrows; r += gridDim.x * TPB) {
+    const int n = S.nrows + S.nm;
+    const long long Nh = S.N2 >> 1;
+    for (int r = blockIdx.x * TPB + threadIdx.x; r < n; r += gridDim.x * TPB) {
+        if (r >= S.nrows) {
+            const int m = r - S.nrows;
+            if (S.mcolor[m] == color) st(x, S.mslot[m], mtmp[m]);
+            continue;
+        }
         const double bv = ld(b, ghost_unknown(S, r)), sg = S.rsG[r];
-        tmp[r] = ghost_sum(S, x, r) - bv / sg;
+        int32_t gc[8], gm[8];
+        double gw[8], xv[8];
+        ghost_stencil(S, r, gc, gw);
+        if (S.nm) {
+            const int4 *m4 = reinterpret_cast<const int4 *>(S.rmrow + 8 * (long long)r);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int4 q = m4[t];
+                gm[4 * t] = q.x; gm[4 * t + 1] = q.y; gm[4 * t + 2] = q.z; gm[4 * t + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) gm[t] = -1;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const bool fresh = gm[t] >= 0 && (gc[t] >= Nh) == (color == 1);
+            xv[t] = fresh ? round_to<T>(mtmp[gm[t]]) : ld(x, gc[t] >= 0 ? (long long)gc[t] : 0LL);
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (gc[t] >= 0) acc += gw[t] * xv[t];
+        gtmp[r] = acc - bv / sg;
     }
 }
 

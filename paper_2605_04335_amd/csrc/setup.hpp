@@ -49,6 +49,29 @@ __global__ void __launch_bounds__(TPB) k_setup_rows(SlotMap m, long long ng, lon
     }
 }
 
+// membrane cell behind each ghost-row stencil column: its index in the
+// sorted membrane cell list, or -1 (not a grid cell, or not a membrane cell)
+__global__ void __launch_bounds__(TPB) k_map_mrows(long long n, const int32_t *__restrict__ col, long long N,
+                                                   const uint8_t *__restrict__ flags,
+                                                   const int32_t *__restrict__ mcell, long long nm,
+                                                   int32_t *__restrict__ out)
+{
+    for (long long q = blockIdx.x * (long long)TPB + threadIdx.x; q < n; q += (long long)gridDim.x * TPB) {
+        const int32_t v = col[q];
+        int32_t o = -1;
+        if (v >= 0 && v < N && (flags[v] & F_MGHOST)) {
+            long long a = 0, e = nm;  // first index with mcell >= v
+            while (a < e) {
+                const long long h = (a + e) >> 1;
+                if (mcell[h] < v) a = h + 1;
+                else e = h;
+            }
+            if (a < nm && mcell[a] == v) o = (int32_t)a;
+        }
+        out[q] = o;
+    }
+}
+
 // membrane-adjacent cells: slot, colour, and the unknown behind each face
 // (-x, +x, -y, +y, -z, +z): the neighbour cell, or the neighbour's ghost
 // unknown when the link is cut (-1 at a wall).  mcell is sorted; a cut link

@@ -152,6 +152,7 @@ struct poisson_ctx {
     int tail0d = 1;            // the same for FP64 levels
     std::vector<double> srj_w; // SRJ relaxation factors in application order
     DBuf<int32_t> rslot, rcol, mslot, mcol, mcolor;
+    DBuf<int32_t> rmrow;  // membrane cell behind each ghost-row column
     DBuf<double> rw, rsG, rdlb;
     std::vector<Level> lv;
     Sp sp;
@@ -165,7 +166,7 @@ struct poisson_ctx {
     // rounding by up to |A| ~ 12/h^2)
     DBuf<double> d64;
     DBuf<double> r2;           // mixed: right-hand side of the FP64 fallback solve
-    DBuf<double> gtmp, sc, part;
+    DBuf<double> gtmp, mtmp, sc, part;  // ghost and membrane staging; scalars; partials
     DBuf<double> ssum;          // set-up sums (fluid volume, active volume per level)
     DBuf<int> serr;             // set-up error flag
     DBuf<uint8_t> hact[2];      // set-up: natural-order coarse active/cut bits of two consecutive levels
@@ -321,7 +322,7 @@ template <class T>
 void fine_smooth(poisson_ctx &c, T *x, const T *b, const double *sink, bool from_zero, hipStream_t s)
 {
     const Level &L = c.lv[0];
-    const int mb = sparse_blocks(c.nm), gb = sparse_blocks(c.nrows);
+    const int mb = sparse_blocks(c.nm), gb = sparse_blocks(c.nrows + c.nm);
     for (int color = 0; color < 2; ++color) {
         if (from_zero && color == 0) {
             // the other colour is zeroed too: ghost rows and membrane rows read it before its sweep
@@ -341,12 +342,9 @@ void fine_smooth(poisson_ctx &c, T *x, const T *b, const double *sink, bool from
                                                  sink, color);
             if (!from_zero) prof_end(c, PK_SWEEP0, s);
         }
-        if (c.nm) {
-            k0_msweep<T><<<mb, TPB, 0, s>>>(L.lv, c.sp, x, b, color, c.gtmp.p);
-            k0_mscat<T><<<mb, TPB, 0, s>>>(c.sp, x, color, c.gtmp.p);
-        }
+        if (c.nm) k0_msweep<T><<<mb, TPB, 0, s>>>(L.lv, c.sp, x, b, color, c.mtmp.p);
         if (c.nrows) {
-            k0_gjac<T><<<gb, TPB, 0, s>>>(c.sp, x, b, c.gtmp.p);
+            k0_mscat_gjac<T><<<gb, TPB, 0, s>>>(c.sp, x, b, color, c.mtmp.p, c.gtmp.p);
             k0_gscat<T><<<gb, TPB, 0, s>>>(c.sp, x, c.gtmp.p);
         }
     }
@@ -750,6 +748,8 @@ void setup_geometry(poisson_ctx &c, const uint8_t *flags, const ibm_stencils *st
     reserve(c.rsG, R1);
     reserve(c.rdlb, R1);
     reserve(c.gtmp, R1);
+    reserve(c.mtmp, M1);
+    reserve(c.rmrow, R1 * 8);
     reserve(c.mslot, M1);
     reserve(c.mcol, M1 * 6);
     reserve(c.mcolor, M1);
@@ -764,6 +764,8 @@ void setup_geometry(poisson_ctx &c, const uint8_t *flags, const ibm_stencils *st
     if (nm)
         k_setup_membrane<<<blocks(nm), TPB, 0, s>>>(sm, nz, nm, st->cell.p + c.ng, flags, c.mslot.p, c.mcol.p,
                                                     c.mcolor.p, c.serr.p);
+    if (R && nm)
+        k_map_mrows<<<blocks(8 * R), TPB, 0, s>>>(8 * R, st->col.p, N, flags, st->cell.p + c.ng, nm, c.rmrow.p);
     // the slots those rows read (the first half-sweep of a V-cycle zeroes
     // these, not every black slot)
     if (R) k_mark_read<<<blocks(8 * R), TPB, 0, s>>>(8 * R, c.rcol.p, c.N2, Z.m.p);
@@ -800,6 +802,7 @@ void setup_geometry(poisson_ctx &c, const uint8_t *flags, const ibm_stencils *st
     S.rslot = c.rslot.p; S.rcol = c.rcol.p; S.rw = c.rw.p; S.rsG = c.rsG.p;
     S.nm = (int)nm;
     S.mslot = c.mslot.p; S.mcol = c.mcol.p; S.mcolor = c.mcolor.p;
+    S.rmrow = c.rmrow.p;
     // vectors over the unknowns: exact size at set-up; when an update needs
     // more, every held vector is reallocated with headroom for later updates
     const long long Nt = c.N2 + nm;
