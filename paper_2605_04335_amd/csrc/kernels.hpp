@@ -1672,6 +1672,7 @@ __global__ void __launch_bounds__(TPB) k_prolong_z(Lv F, Lv C, PMap M, Geo Gc, c
 // reductions.  Only the first tail level's RHS comes from global memory and
 // only its iterate goes back.
 constexpr int TAIL_T = 1024;
+static_assert(TAIL_T >= 8 * 128, "the tail stages each of up to 8 levels with 128 threads");
 constexpr int TAIL_LDS = 60 * 1024;  // bytes of dynamic LDS the tail may use
 
 struct TailLevel {
@@ -1686,7 +1687,15 @@ struct Tail {
     int n;            // levels in the tail (>= 1)
     TailLevel t[8];
     int nu1, nu2, ncs;
+    int coff;         // LDS byte offset of the levels' coefficient copies
 };
+
+// LDS bytes of one tail level's coefficient copies: cp, cm, w and the
+// prolongation weights pt (double), then the map pi (int), per axis
+__host__ __device__ inline int tail_coef_bytes(int nx, int ny, int nz)
+{
+    return (36 * (nx + ny + nz) + 15) / 16 * 16;
+}
 
 __device__ double tail_sum(double v)
 {
@@ -1703,13 +1712,42 @@ __device__ double tail_sum(double v)
     return s;
 }
 
+// nbsum<false> for an LDS-resident tail level without branches: every
+// neighbour value and coefficient is loaded (a closed face reads the cell's
+// own slot) and a closed face's coefficient is replaced by zero, so all six
+// loads are in flight together.  Adding a zero product or a zero
+// coefficient leaves the sums unchanged, so the result is nbsum's.
+template <class T>
+__device__ __forceinline__ double nbsum_lds(const Lv &L, const T *xo, int h, int j, int k, int i, uint8_t fm,
+                                            double &dg)
+{
+    const int p = i & 1;
+    const int pl = L.H * L.ny, base = h + L.H * j + pl * k;
+    const bool o[6] = {(fm & CM_PX) != 0, (fm & CM_MX) != 0, (fm & CM_PY) != 0,
+                       (fm & CM_MY) != 0, (fm & CM_PZ) != 0, (fm & CM_MZ) != 0};
+    const int dx[6] = {p, p - 1, L.H, -L.H, pl, -pl};
+    const double cv[6] = {L.cp[0][i], L.cm[0][i], L.cp[1][j], L.cm[1][j], L.cp[2][k], L.cm[2][k]};
+    double xv[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) xv[t] = ld(xo, base + (o[t] ? dx[t] : 0));
+    double acc = 0.0, d = 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const double c = o[t] ? cv[t] : 0.0;
+        acc += c * xv[t];
+        d += c;
+    }
+    dg = d;
+    return acc;
+}
+
 template <class Tc>
 __device__ void tail_sweep(const Lv &L, Tc *x, const Tc *b, double mu, int c, bool zero)
 {
     const int n = L.H * L.ny * L.nz;  // a tail level fits in LDS: 32-bit indices
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        const int h = q % L.H, row = q / L.H;
-        const int j = row % L.ny, k = row / L.ny;
+        const int row = (int)fdiv((uint32_t)q, L.fH), h = q - row * L.H;
+        const int k = (int)fdiv((uint32_t)row, L.fy), j = row - k * L.ny;
         const long long s = (long long)c * L.Nh + q;
         const uint8_t f = L.f[s];
         const int i = 2 * h + ((c + j + k) & 1);
@@ -1722,7 +1760,7 @@ __device__ void tail_sweep(const Lv &L, Tc *x, const Tc *b, double mu, int c, bo
             off = 0.0;
             dg = diag_only<false>(L, L.f + L.Nh, h, j, k, i, f);
         } else {
-            off = nbsum<false>(L, x + (long long)(1 - c) * L.Nh, L.f + (long long)(1 - c) * L.Nh, h, j, k, i, f, dg);
+            off = nbsum_lds(L, x + (long long)(1 - c) * L.Nh, h, j, k, i, f, dg);
         }
         st(x, s, dg > 0.0 ? (off - (ld(b, s) - mu)) / dg : 0.0);
     }
@@ -1746,6 +1784,9 @@ __device__ void tail_coarsest_wave(const Lv &L, Tc *x, const Tc *b, double mu, i
 {
     const int lane = threadIdx.x & 63;
     const int n = L.H * L.ny * L.nz;  // <= 64
+    // a closed face keeps the cell's own slot with a zero coefficient, so the
+    // six loads of a half-sweep go out without branches (adding zero
+    // products leaves the sum as it was)
     int nb[2][6];
     double cf[2][6], dg[2], bm[2];
     bool act[2];
@@ -1755,11 +1796,12 @@ __device__ void tail_coarsest_wave(const Lv &L, Tc *x, const Tc *b, double mu, i
         dg[c] = bm[c] = 0.0;
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
-            nb[c][t] = -1;
+            nb[c][t] = c * (int)L.Nh;
             cf[c][t] = 0.0;
         }
         if (lane >= n) continue;
-        const int h = lane % L.H, row = lane / L.H, j = row % L.ny, k = row / L.ny;
+        const int row = (int)fdiv((uint32_t)lane, L.fH), h = lane - row * L.H;
+        const int k = (int)fdiv((uint32_t)row, L.fy), j = row - k * L.ny;
         const int s = c * (int)L.Nh + lane;
         const uint8_t f = L.f[s];
         const int i = 2 * h + ((c + j + k) & 1);
@@ -1777,6 +1819,8 @@ __device__ void tail_coarsest_wave(const Lv &L, Tc *x, const Tc *b, double mu, i
                 nb[c][t] = o + off[t];
                 cf[c][t] = cv[t];
                 d += cv[t];
+            } else {
+                nb[c][t] = o;
             }
         dg[c] = d;
         bm[c] = ld(b, s) - mu;
@@ -1787,9 +1831,11 @@ __device__ void tail_coarsest_wave(const Lv &L, Tc *x, const Tc *b, double mu, i
             if (act[c]) {
                 double acc = 0.0;
                 if (it > 0 || c == 1) {
+                    double xv[6];
 #pragma unroll
-                    for (int t = 0; t < 6; ++t)
-                        if (nb[c][t] >= 0) acc += cf[c][t] * ld(x, nb[c][t]);
+                    for (int t = 0; t < 6; ++t) xv[t] = ld(x, nb[c][t]);
+#pragma unroll
+                    for (int t = 0; t < 6; ++t) acc += cf[c][t] * xv[t];
                 }
                 st(x, c * L.Nh + lane, dg[c] > 0.0 ? (acc - bm[c]) / dg[c] : 0.0);
             } else if (it == 0 && lane < n) {
@@ -1800,12 +1846,57 @@ __device__ void tail_coarsest_wave(const Lv &L, Tc *x, const Tc *b, double mu, i
     }
 }
 
-// view of tail level l whose mask lives in LDS
-__device__ __forceinline__ Lv tail_lv(const Tail &T, int l, unsigned char *smem)
+// byte offset of tail level l's coefficient copies
+__device__ __forceinline__ int tail_coef_off(const Tail &T, int l)
+{
+    int o = T.coff;
+    for (int q = 0; q < l; ++q) o += tail_coef_bytes(T.t[q].L.nx, T.t[q].L.ny, T.t[q].L.nz);
+    return o;
+}
+
+// view of tail level l whose mask and coefficients live in LDS (the
+// prolongation map onto it from the next level in *M)
+__device__ __forceinline__ Lv tail_lv(const Tail &T, int l, unsigned char *smem, PMap *M = nullptr)
 {
     Lv L = T.t[l].L;
     L.f = (const uint8_t *)(smem + T.t[l].moff);
+    const int n[3] = {L.nx, L.ny, L.nz}, nt = L.nx + L.ny + L.nz;
+    double *dp = (double *)(smem + tail_coef_off(T, l));
+    int *ip = (int *)(dp + 4 * nt);
+    for (int d = 0; d < 3; ++d) {
+        L.cp[d] = dp;
+        L.cm[d] = dp + n[d];
+        L.w[d] = dp + 2 * n[d];
+        if (M) {
+            M->pt[d] = dp + 3 * n[d];
+            M->pi[d] = ip;
+        }
+        dp += 4 * n[d];
+        ip += n[d];
+    }
     return L;
+}
+
+// copy tail level l's coefficients (and, below the last level, its
+// prolongation map) from global memory into LDS, threads t0, t0 + nt, ...
+__device__ __forceinline__ void tail_stage_coef(const Tail &T, int l, unsigned char *smem, int t0, int nt)
+{
+    const Lv &G = T.t[l].L;
+    const PMap &GM = T.t[l].M;
+    const bool map = l < T.n - 1;
+    PMap M;
+    Lv L = tail_lv(T, l, smem, &M);
+    const int n[3] = {G.nx, G.ny, G.nz};
+    for (int d = 0; d < 3; ++d)
+        for (int q = t0; q < n[d]; q += nt) {
+            const_cast<double *>(L.cp[d])[q] = G.cp[d][q];
+            const_cast<double *>(L.cm[d])[q] = G.cm[d][q];
+            const_cast<double *>(L.w[d])[q] = G.w[d][q];
+            if (map) {
+                const_cast<double *>(M.pt[d])[q] = GM.pt[d][q];
+                const_cast<int *>(M.pi[d])[q] = GM.pi[d][q];
+            }
+        }
 }
 
 template <class Tc, class TB>
@@ -1813,16 +1904,39 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double mus[8];
-    for (int l = 0; l < T.n; ++l) {
-        uint8_t *m = (uint8_t *)(smem + T.t[l].moff);
-        const long long n2 = 2 * T.t[l].L.Nh;
-        for (long long q = threadIdx.x; q < n2; q += blockDim.x) m[q] = T.t[l].L.f[q];
+    {
+        // each level is staged by its own 128 threads (at most 8 levels), so
+        // the levels' global loads are in flight together: the mask in
+        // 16-byte pieces, then the coefficients
+        const int l = threadIdx.x >> 7, t0 = threadIdx.x & 127;
+        if (l < T.n) {
+            const TailLevel &TL = T.t[l];
+            uint8_t *m = (uint8_t *)(smem + TL.moff);
+            const long long n2 = 2 * TL.L.Nh, n16 = n2 >> 4;
+            for (long long q = t0; q < n16; q += 128)
+                reinterpret_cast<uint4 *>(m)[q] = reinterpret_cast<const uint4 *>(TL.L.f)[q];
+            for (long long q = 16 * n16 + t0; q < n2; q += 128) m[q] = TL.L.f[q];
+            tail_stage_coef(T, l, smem, t0, 128);
+        }
     }
     {
+        // the first tail level's RHS, four loads per thread in flight
         Tc *b0 = (Tc *)(smem + T.t[0].boff);
         const TB *bg = (const TB *)T.t[0].bg;
         const long long n2 = 2 * T.t[0].L.Nh;
-        for (long long q = threadIdx.x; q < n2; q += blockDim.x) b0[q] = (Tc)ld(bg, q);
+        for (long long q0 = threadIdx.x; q0 < n2; q0 += 4 * (long long)blockDim.x) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const long long q = q0 + u * (long long)blockDim.x;
+                v[u] = q < n2 ? ld(bg, q) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const long long q = q0 + u * (long long)blockDim.x;
+                if (q < n2) b0[q] = (Tc)v[u];
+            }
+        }
     }
     if (threadIdx.x == 0) mus[0] = mean0[0];
     __syncthreads();
@@ -1851,8 +1965,8 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
         for (int q = threadIdx.x; q < 2 * nc; q += blockDim.x) {
             const int cc = q >= nc ? 1 : 0;
             const int qq = q - cc * nc;
-            const int hc = qq % C.H, row = qq / C.H;
-            const int J = row % C.ny, K = row / C.ny;
+            const int row = (int)fdiv((uint32_t)qq, C.fH), hc = qq - row * C.H;
+            const int K = (int)fdiv((uint32_t)row, C.fy), J = row - K * C.ny;
             double mub = mu;
             restrict_one<false, Tc, Tc, Tc>(L, C, -1, x, b, &mub, (const Tc *)nullptr, bc, cc, hc, J, K);
             const long long sc = (long long)cc * C.Nh + qq;
@@ -1864,8 +1978,8 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
             if (!(C.f[q] & 1)) continue;
             const int cc = q >= nc ? 1 : 0;
             const int qq = q - cc * nc;
-            const int hc = qq % C.H, row = qq / C.H;
-            const int J = row % C.ny, K = row / C.ny;
+            const int row = (int)fdiv((uint32_t)qq, C.fH), hc = qq - row * C.H;
+            const int K = (int)fdiv((uint32_t)row, C.fy), J = row - K * C.ny;
             const int I = 2 * hc + ((cc + J + K) & 1);
             part += C.w[0][I] * C.w[1][J] * C.w[2][K] * ld(bc, q);
         }
@@ -1874,15 +1988,17 @@ __global__ void __launch_bounds__(TAIL_T) k_tail(Tail T, const double *mean0)
         __syncthreads();
     }
     for (int l = T.n - 2; l >= 0; --l) {
-        const Lv L = tail_lv(T, l, smem), C = tail_lv(T, l + 1, smem);
+        PMap M;
+        const Lv L = tail_lv(T, l, smem, &M), C = tail_lv(T, l + 1, smem);
         Tc *x = (Tc *)(smem + T.t[l].xoff);
         const Tc *xc = (const Tc *)(smem + T.t[l + 1].xoff);
         const int n = L.H * L.ny * L.nz;
         for (int q = threadIdx.x; q < 2 * n; q += blockDim.x) {
             const int c = q >= n ? 1 : 0;
             const int qq = q - c * n;
-            const int h = qq % L.H, row = qq / L.H;
-            prolong_one<false>(L, C, T.t[l].M, xc, x, c, h, row % L.ny, row / L.ny);
+            const int row = (int)fdiv((uint32_t)qq, L.fH), h = qq - row * L.H;
+            const int k = (int)fdiv((uint32_t)row, L.fy);
+            prolong_one<false>(L, C, M, xc, x, c, h, row - k * L.ny, k);
         }
         __syncthreads();
         const Tc *b = (const Tc *)(smem + T.t[l].boff);

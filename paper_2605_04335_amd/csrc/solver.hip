@@ -420,6 +420,11 @@ void vcycle(poisson_ctx &c, const T *b, T *x, const double *sink, hipStream_t s)
                 tl.t[q].bg = Store<T>::b(L);
                 tail_layout(L.Nh, sizeof(Tc), off, tl.t[q].moff, tl.t[q].xoff, tl.t[q].boff);
             }
+            tl.coff = off;
+            for (int q = 0; q < tl.n; ++q) {
+                const Level &L = c.lv[lt + q];
+                off += tail_coef_bytes(L.n[0], L.n[1], L.n[2]);
+            }
             k_tail<Tc, TB><<<1, TAIL_T, off, s>>>(tl, c.sc.p + S_MEAN0 + lt);
             IBM_LAUNCH_CHECK();
         }
@@ -919,6 +924,7 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
         for (int l = nl - 1; l >= 1 && (nl - l) <= 8; --l) {
             int m, xo, bo, o2 = off;
             tail_layout(c->lv[l].Nh, tsz, o2, m, xo, bo);
+            o2 += tail_coef_bytes(c->lv[l].n[0], c->lv[l].n[1], c->lv[l].n[2]);
             if (o2 > TAIL_LDS) break;
             off = o2;
             t0 = l;
