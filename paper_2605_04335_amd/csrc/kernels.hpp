@@ -252,6 +252,36 @@ __device__ __forceinline__ double nbsum(const Lv &L, const T *xo, const uint8_t 
     return acc;
 }
 
+// nbsum<false> without branches: every neighbour value and coefficient is
+// loaded (a closed face reads the cell's own slot in the other colour) and a
+// closed face's coefficient is replaced by zero, so all six loads are in
+// flight together.  Adding a zero product or a zero coefficient leaves the
+// sums unchanged (the sums are never -0), so the result is nbsum's.  Used
+// where the level is LDS-resident (the coarse tail).
+template <class T>
+__device__ __forceinline__ double nbsum_all(const Lv &L, const T *xo, int h, int j, int k, int i, uint8_t fm,
+                                            double &dg)
+{
+    const int p = i & 1;
+    const int pl = L.H * L.ny, base = h + L.H * j + pl * k;
+    const bool o[6] = {(fm & CM_PX) != 0, (fm & CM_MX) != 0, (fm & CM_PY) != 0,
+                       (fm & CM_MY) != 0, (fm & CM_PZ) != 0, (fm & CM_MZ) != 0};
+    const int dx[6] = {p, p - 1, L.H, -L.H, pl, -pl};
+    const double cv[6] = {L.cp[0][i], L.cm[0][i], L.cp[1][j], L.cm[1][j], L.cp[2][k], L.cm[2][k]};
+    double xv[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) xv[t] = ld(xo, base + (o[t] ? dx[t] : 0));
+    double acc = 0.0, d = 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const double c = o[t] ? cv[t] : 0.0;
+        acc += c * xv[t];
+        d += c;
+    }
+    dg = d;
+    return acc;
+}
+
 // the diagonal alone (no vector is read): sum of the open faces' coefficients
 template <bool FINE>
 __device__ __forceinline__ double diag_only(const Lv &L, const uint8_t *fo, int h, int j, int k, int i, uint8_t fm)
@@ -1182,7 +1212,7 @@ __device__ __forceinline__ bool child_res(const Lv &F, long long pin, const T *x
     } else {
         if (!(f & 1)) return false;
         double dg;
-        double off = nbsum<false>(F, x + (long long)(1 - cf) * F.Nh, F.f + (long long)(1 - cf) * F.Nh, h, j, k, i, f, dg);
+        double off = nbsum_all(F, x + (long long)(1 - cf) * F.Nh, h, j, k, i, f, dg);
         r = ld(b, so + s) - (bsh ? bsh[0] : 0.0) - (off - dg * ld(x, so + s));
         return true;
     }
@@ -1712,35 +1742,6 @@ __device__ double tail_sum(double v)
     return s;
 }
 
-// nbsum<false> for an LDS-resident tail level without branches: every
-// neighbour value and coefficient is loaded (a closed face reads the cell's
-// own slot) and a closed face's coefficient is replaced by zero, so all six
-// loads are in flight together.  Adding a zero product or a zero
-// coefficient leaves the sums unchanged, so the result is nbsum's.
-template <class T>
-__device__ __forceinline__ double nbsum_lds(const Lv &L, const T *xo, int h, int j, int k, int i, uint8_t fm,
-                                            double &dg)
-{
-    const int p = i & 1;
-    const int pl = L.H * L.ny, base = h + L.H * j + pl * k;
-    const bool o[6] = {(fm & CM_PX) != 0, (fm & CM_MX) != 0, (fm & CM_PY) != 0,
-                       (fm & CM_MY) != 0, (fm & CM_PZ) != 0, (fm & CM_MZ) != 0};
-    const int dx[6] = {p, p - 1, L.H, -L.H, pl, -pl};
-    const double cv[6] = {L.cp[0][i], L.cm[0][i], L.cp[1][j], L.cm[1][j], L.cp[2][k], L.cm[2][k]};
-    double xv[6];
-#pragma unroll
-    for (int t = 0; t < 6; ++t) xv[t] = ld(xo, base + (o[t] ? dx[t] : 0));
-    double acc = 0.0, d = 0.0;
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        const double c = o[t] ? cv[t] : 0.0;
-        acc += c * xv[t];
-        d += c;
-    }
-    dg = d;
-    return acc;
-}
-
 template <class Tc>
 __device__ void tail_sweep(const Lv &L, Tc *x, const Tc *b, double mu, int c, bool zero)
 {
@@ -1760,7 +1761,7 @@ __device__ void tail_sweep(const Lv &L, Tc *x, const Tc *b, double mu, int c, bo
             off = 0.0;
             dg = diag_only<false>(L, L.f + L.Nh, h, j, k, i, f);
         } else {
-            off = nbsum_lds(L, x + (long long)(1 - c) * L.Nh, h, j, k, i, f, dg);
+            off = nbsum_all(L, x + (long long)(1 - c) * L.Nh, h, j, k, i, f, dg);
         }
         st(x, s, dg > 0.0 ? (off - (ld(b, s) - mu)) / dg : 0.0);
     }
