@@ -454,9 +454,10 @@ def main():
                     help="HBM budget (GB) of a second run at the highest rate, where admission binds; 0: skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with three plain 1 GiB stream copies (reference for HBM byte counters)")
-    ap.add_argument("--profile", default="none", choices=["none", "mixed", "stream"],
+    ap.add_argument("--profile", default="none", choices=["none", "mixed", "stream", "moving"],
                     help="profiler runs: 'mixed' times only the mixed form (--warmup and --steps solves and one "
-                         "with per-launch sweep timing), 'stream' only the streaming ceiling")
+                         "with per-launch sweep timing), 'stream' only the streaming ceiling, 'moving' only the "
+                         "moving-body steps and the advection-diffusion step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PPE solve runs on a single MI355X; "
@@ -474,6 +475,9 @@ def main():
         if args.copy_calibration:
             P.hbm_stream(P.STREAM_COPY, 1 << 30, 3)
         print(json.dumps(out), flush=True)
+        return
+    if args.profile == "moving":
+        print(json.dumps({"moving": moving_bench(P), "advection_diffusion": ad_bench(P)}), flush=True)
         return
     p, desc = make_problem(args.config)
     nx, ny, nz = p.shape
