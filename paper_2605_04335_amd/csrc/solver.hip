@@ -690,7 +690,7 @@ size_t estimate_bytes(int nx, int ny, int nz, long long nrows, int precision)
     long long Nh = (long long)((nx + 1) / 2) * ny * nz;
     long long Nt = 2 * Nh + nrows;
     size_t b = (size_t)2 * Nh;  // flags
-    b += (size_t)nrows * (8 * 4 + 8 * 8 + 16 + 8 + 4 + 6 * 4 + 4);
+    b += (size_t)nrows * (8 * 4 + 8 * 8 + 16 + 8 + 4 + 6 * 4 + 4 + 8 * 4 + 8);
     b += (size_t)Nt * 8 * (precision == IBM_PREC_MIXED ? 4 : 10);
     if (precision == IBM_PREC_MIXED) b += (size_t)Nt * (4 * 8 + 8);
     long long Nc = 2 * Nh;
