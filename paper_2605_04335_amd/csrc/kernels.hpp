@@ -133,6 +133,20 @@ inline Geo make_geo(int H, int ny, int nz, int maxb = 8192)
     g.nb = (int)((n + 7) / 8 * 8);
     return g;
 }
+// tiles of 64 half-indices x 8 rows for a kernel whose threads take two
+// consecutive rows each (the FP64 level-0 half-sweep)
+inline Geo make_geo_rows2(int H, int ny, int nz, int maxb = 8192)
+{
+    Geo g = make_geo(H, ny, nz, maxb);
+    g.gy = (ny + 7) / 8;
+    const long long xy = (long long)g.gx * g.gy;
+    int kz = 1;
+    while (xy * ((nz + kz - 1) / kz) > maxb && kz < nz) kz *= 2;
+    g.kz = kz;
+    g.gz = (nz + kz - 1) / kz;
+    g.nb = (int)((xy * g.gz + 7) / 8 * 8);
+    return g;
+}
 // tiles over cells in natural x order (nx instead of H): the restriction
 inline Geo make_geo_nat(int nx, int ny, int nz, int maxb = 8192) { return make_geo(nx, ny, nz, maxb); }
 
@@ -610,6 +624,120 @@ __global__ void __launch_bounds__(TPB) k_csweep(Lv L, Geo G, T *__restrict__ x, 
 // is a later half-sweep, long after a level-0 vector has left the caches.
 // pin_s: the pin's slot within this colour (or -1), whose RHS carries the sink.
 template <class T>
+__device__ __forceinline__ void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
+
+// FP64: each thread updates two consecutive rows j0, j0 + 1 of its column
+// (tiles of 64 x 8 from make_geo_rows2).  The other colour's centres of both
+// rows are in the window, and they are row j0's y+ neighbour and row j0+1's
+// y- neighbour, so a step loads 10 values for 2 cells instead of 12
+// (5.5% faster at 512^3; FP32 is faster with the one-row form).  Same
+// arithmetic, in the same order, per cell.
+__device__ __forceinline__ bool geo_tile2(const Geo &G, int &h, int &j0, int &k0, int &k1)
+{
+    const int b = blockIdx.x;
+    const int L = (b & 7) * (G.nb >> 3) + (b >> 3);
+    const int bx = L % G.gx, r = L / G.gx, by = r % G.gy, bz = r / G.gy;
+    if (bz >= G.gz) return false;
+    h = bx * 64 + (threadIdx.x & 63);
+    j0 = by * 8 + 2 * (threadIdx.x >> 6);
+    k0 = bz * G.kz;
+    k1 = min(G.nz, k0 + G.kz);
+    return h < G.H && j0 < G.ny;
+}
+
+template <class T>
+__device__ __forceinline__ void sweep_rows2(const Lv &L, const Geo &G, long long pin_s, T *__restrict__ xc,
+                                            const T *__restrict__ xo, const T *__restrict__ bc,
+                                            const uint8_t *__restrict__ fc, const double *__restrict__ sink, int c)
+{
+    constexpr int UP = 2;
+    int h, j0, k0, k1;
+    if (!geo_tile2(G, h, j0, k0, k1)) return;
+    const bool two = j0 + 1 < L.ny;  // an odd last row is updated alone
+    const int j1 = two ? j0 + 1 : j0;
+    const Col0 qa = col0(L, c, h, j0), qb = col0(L, c, h, j1);
+    const uint32_t pl = (uint32_t)(L.H * L.ny);
+    const int kb = max(k0 - 1, 0);
+    const T *xb = xo + (long long)pl * kb;
+    const T *bp = bc + (long long)pl * kb;
+    const uint8_t *fb = fc + (long long)pl * kb;
+    T *xw = xc + (long long)pl * kb;
+    const uint32_t ca = (uint32_t)(h + L.H * j0), cb = (uint32_t)(h + L.H * j1);
+    const int oxa0 = qa.oxp[0] + qa.oxm[0], oxa1 = qa.oxp[1] + qa.oxm[1];
+    const int oxb0 = qb.oxp[0] + qb.oxm[0], oxb1 = qb.oxp[1] + qb.oxm[1];
+    const int oyma = (int)qa.oym, oypb = (int)qb.oyp;  // the two loaded y neighbours
+    const long long pin_rel = pin_s >= 0 ? pin_s - (long long)pl * kb : -1;
+    // centres of both rows in planes k-1 and k
+    double pa = k0 > 0 ? (double)ldu(xb, ca + pl * (uint32_t)(k0 - 1 - kb)) : 0.0;
+    double pb = k0 > 0 ? (double)ldu(xb, cb + pl * (uint32_t)(k0 - 1 - kb)) : 0.0;
+    double ua = ldu(xb, ca + pl * (uint32_t)(k0 - kb));
+    double ub = ldu(xb, cb + pl * (uint32_t)(k0 - kb));
+    for (int ks = k0; ks < k1; ks += UP) {
+        double na[UP], nb2[UP], xa[UP], xbb[UP], ym[UP], yp[UP], ba[UP], bb[UP], czp[UP], czm[UP];
+        uint8_t fa[UP], fbb[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+            const int k = min(ks + u, k1 - 1);
+            const int kn = min(k + 1, L.nz - 1);
+            const uint32_t sa = ca + pl * (uint32_t)(k - kb), sb = cb + pl * (uint32_t)(k - kb);
+            const bool t = k & 1;
+            na[u] = ldu(xb, ca + pl * (uint32_t)(kn - kb));  // centres of plane k+1
+            nb2[u] = ldu(xb, cb + pl * (uint32_t)(kn - kb));
+            xa[u] = ldu(xb, sa + (uint32_t)(t ? oxa1 : oxa0));
+            xbb[u] = ldu(xb, sb + (uint32_t)(t ? oxb1 : oxb0));
+            ym[u] = ldu(xb, sa + (uint32_t)oyma);
+            yp[u] = ldu(xb, sb + (uint32_t)oypb);
+            fa[u] = ldu(fb, sa);
+            fbb[u] = ldu(fb, sb);
+            ba[u] = ldu(bp, sa);
+            bb[u] = ldu(bp, sb);
+            czp[u] = L.cp[2][k];  // zero at the walls
+            czm[u] = L.cm[2][k];
+        }
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+            const int k = ks + u;
+            const double cca = u == 0 ? ua : na[u - 1], ccb = u == 0 ? ub : nb2[u - 1];
+            const double cma = u == 0 ? pa : (u == 1 ? ua : na[u - 2]);
+            const double cmb = u == 0 ? pb : (u == 1 ? ub : nb2[u - 2]);
+            if (k >= k1) continue;
+            const bool t = k & 1;
+            {   // row j0: its y+ neighbour is row j1's centre (its own centre when alone)
+                const uint32_t s = ca + pl * (uint32_t)(k - kb);
+                const double cpx = t ? qa.cpx[1] : qa.cpx[0], cmx = t ? qa.cmx[1] : qa.cmx[0];
+                const int oxp = t ? qa.oxp[1] : qa.oxp[0], oxm = t ? qa.oxm[1] : qa.oxm[0];
+                const double xpv = oxp == 0 ? cca : xa[u], xmv = oxm == 0 ? cca : xa[u];
+                const double ypk = two ? ccb : cca;
+                const double dg = cpx + cmx + qa.cpy + qa.cmy + czp[u] + czm[u];
+                const double nb = cpx * xpv + cmx * xmv + qa.cpy * ypk + qa.cmy * ym[u] + czp[u] * na[u] + czm[u] * cma;
+                if (!(fa[u] & (F_SOLID | F_MGHOST))) {
+                    double b0 = ba[u];
+                    if ((long long)s == pin_rel) b0 -= sink[0];
+                    st_nt(xw + s, (T)((nb - b0) / dg));
+                }
+            }
+            if (two) {  // row j1: its y- neighbour is row j0's centre
+                const uint32_t s = cb + pl * (uint32_t)(k - kb);
+                const double cpx = t ? qb.cpx[1] : qb.cpx[0], cmx = t ? qb.cmx[1] : qb.cmx[0];
+                const int oxp = t ? qb.oxp[1] : qb.oxp[0], oxm = t ? qb.oxm[1] : qb.oxm[0];
+                const double xpv = oxp == 0 ? ccb : xbb[u], xmv = oxm == 0 ? ccb : xbb[u];
+                const double dg = cpx + cmx + qb.cpy + qb.cmy + czp[u] + czm[u];
+                const double nb = cpx * xpv + cmx * xmv + qb.cpy * yp[u] + qb.cmy * cca + czp[u] * nb2[u] + czm[u] * cmb;
+                if (!(fbb[u] & (F_SOLID | F_MGHOST))) {
+                    double b0 = bb[u];
+                    if ((long long)s == pin_rel) b0 -= sink[0];
+                    st_nt(xw + s, (T)((nb - b0) / dg));
+                }
+            }
+        }
+        pa = na[UP - 2];
+        pb = nb2[UP - 2];
+        ua = na[UP - 1];
+        ub = nb2[UP - 1];
+    }
+}
+
+template <class T>
 struct SweepPlanes {
     static constexpr int n = 2;
 };
@@ -617,9 +745,6 @@ template <>
 struct SweepPlanes<float> {
     static constexpr int n = 4;
 };
-
-template <class T>
-__device__ __forceinline__ void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
 
 // byte offsets of a tile's planes fit in 32 bits
 inline bool plane_span_ok(long long plane_slots, int kz, size_t elem) { return plane_slots * (kz + 2) * (long long)elem < (1LL << 32); }
@@ -629,6 +754,10 @@ __global__ void __launch_bounds__(TPB) k0_sweep(Lv L, Geo G, long long pin_s, T 
                                                 const T *__restrict__ xo, const T *__restrict__ bc,
                                                 const uint8_t *__restrict__ fc, const double *__restrict__ sink, int c)
 {
+    if constexpr (sizeof(T) == 8) {  // G: 64 x 8 tiles (make_geo_rows2)
+        sweep_rows2<T>(L, G, pin_s, xc, xo, bc, fc, sink, c);
+        return;
+    }
     constexpr int UP = SweepPlanes<T>::n;
     // FP32: the x and y neighbours of plane k+1 are loaded with plane k+1's
     // centre, one step ahead of their use, so a step's loads all fall in the

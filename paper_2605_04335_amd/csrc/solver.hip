@@ -50,6 +50,7 @@ struct Level {
     double volA = 0.0;               // volume of the active cells
     long long n_inactive = 0;        // coarse levels: inactive cells (inside bodies)
     Geo geo;                         // tiles over (h, j, k) of one colour
+    Geo geo2;                        // level 0: 64 x 8 tiles of the FP64 half-sweep (two rows per thread)
     Geo geon;                        // tiles over (i, j, k): restriction into this level
     Walk walk;                       // over 2 Nh slots
     DBuf<double> x64, b64;
@@ -338,8 +339,9 @@ void fine_smooth(poisson_ctx &c, T *x, const T *b, const double *sink, bool from
             const long long co = (long long)color * L.Nh;
             const long long pin_s = (sink && c.pin >= co && c.pin < co + L.Nh) ? c.pin - co : -1;
             if (!from_zero) prof_begin(c, PK_SWEEP0, s);
-            k0_sweep<T><<<L.geo.nb, TPB, 0, s>>>(L.lv, L.geo, pin_s, x + co, x + (L.Nh - co), b + co, L.lv.f + co,
-                                                 sink, color);
+            const Geo &G = std::is_same<T, double>::value ? L.geo2 : L.geo;  // FP64: two rows per thread
+            k0_sweep<T><<<G.nb, TPB, 0, s>>>(L.lv, G, pin_s, x + co, x + (L.Nh - co), b + co, L.lv.f + co, sink,
+                                             color);
             if (!from_zero) prof_end(c, PK_SWEEP0, s);
         }
         if (c.nm) k0_msweep<T><<<mb, TPB, 0, s>>>(L.lv, c.sp, x, b, color, c.mtmp.p);
@@ -893,8 +895,10 @@ poisson_ctx *setup(const ibm_grid *grid, const uint8_t *flags, const ibm_stencil
     // level 0: shorter plane runs per thread (more tiles) measured faster;
     // the half-sweep addresses a tile's planes with 32-bit byte offsets
     c->lv[0].geo = make_geo(c->lv[0].H, c->lv[0].n[1], c->lv[0].n[2], 16384);
-    IBM_REQUIRE(plane_span_ok((long long)c->lv[0].H * c->lv[0].n[1], c->lv[0].geo.kz, sizeof(double)), IBM_EINVAL,
-                "grid planes too large for the level-0 sweep's 32-bit offsets");
+    c->lv[0].geo2 = make_geo_rows2(c->lv[0].H, c->lv[0].n[1], c->lv[0].n[2], 8192);
+    IBM_REQUIRE(plane_span_ok((long long)c->lv[0].H * c->lv[0].n[1], std::max(c->lv[0].geo.kz, c->lv[0].geo2.kz),
+                              sizeof(double)),
+                IBM_EINVAL, "grid planes too large for the level-0 sweep's 32-bit offsets");
     c->N2 = 2 * c->lv[0].Nh;
     // prolongation maps of each level from its coarse parent
     for (int l = 1; l < nl; ++l) {
