@@ -446,12 +446,14 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-moving", action="store_true", help="skip the moving-body time-step measurement")
     ap.add_argument("--no-ad", action="store_true", help="skip the advection-diffusion step measurement")
-    ap.add_argument("--serve-rates", default="5,10,20,50,100,200",
-                    help="request arrival rates (req/s) of the serving sweep")
+    ap.add_argument("--serve-rates", default="5,10,20,50",
+                    help="request arrival rates (req/s) of the serving sweep; 100 and 200 are opt-in: a host "
+                         "segmentation fault seen once at 100 req/s is unresolved")
     ap.add_argument("--serve-requests", type=int, default=150, help="requests per arrival rate")
     ap.add_argument("--serve-slots", type=int, default=16, help="concurrently active solves in the server")
-    ap.add_argument("--serve-small-budget-gb", type=int, default=8,
-                    help="HBM budget (GB) of a second run at the highest rate, where admission binds; 0: skip")
+    ap.add_argument("--serve-small-budget-gb", type=int, default=0,
+                    help="HBM budget (GB) of a second run at the highest rate, where admission binds (8 with "
+                         "--serve-rates ...,200 gives the admission-bound case); 0: skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with three plain 1 GiB stream copies (reference for HBM byte counters)")
     ap.add_argument("--profile", default="none", choices=["none", "mixed", "stream", "moving"],
