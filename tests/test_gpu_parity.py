@@ -75,6 +75,18 @@ def cases_small():
         "thin_ellipsoid_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
         [W.ellipsoid((0.5, 0.5, 0.5123), (0.2, 0.15, 0.011), W.rotation_zyx(0.3, 0.0, 0.0), freq=8)])
     out["thin_ellipsoid_40"].f = W.noise_rhs(40 ** 3, 11)
+    # two parallel membranes 0.3 cells apart, overlapping over part of their
+    # chord: a link crossed by both is crossed an even number of times, so it
+    # is not cut
+    out["stacked_plates_40"] = W.Problem(
+        "stacked_plates_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
+        [W.plate((0.45, 0.5, 0.47), 0.3, 0.4, 12, 16, 0.0, 0.0), W.plate((0.55, 0.5, 0.4775), 0.3, 0.4, 12, 16, 0.0, 0.0)])
+    out["stacked_plates_40"].f = W.noise_rhs(40 ** 3, 13)
+    # a cambered membrane that passes through a flat one (intersecting membranes)
+    out["crossing_plates_40"] = W.Problem(
+        "crossing_plates_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
+        [W.plate((0.5, 0.5, 0.5), 0.4, 0.4, 16, 16, 0.0, 0.0), W.plate((0.5, 0.52, 0.475), 0.35, 0.3, 14, 12, 0.05, 0.3)])
+    out["crossing_plates_40"].f = W.noise_rhs(40 ** 3, 14)
     out["empty_box"] = W.Problem("empty_box", W.uniform_faces(16), W.uniform_faces(16), W.uniform_faces(16), [])
     out["empty_box"].f = W.manufactured_rhs(out["empty_box"].xf, out["empty_box"].yf, out["empty_box"].zf)
     return out
@@ -210,7 +222,8 @@ def test_fp64_solve_config_tolerance_c1(torch_cuda):
 
 
 @pytest.mark.parametrize("name", ["c1", "c2_64", "membrane_64", "mixed_bodies_48", "odd_fine", "box_odd",
-                                  "wall_sphere_40", "near_pair_48", "wall_plate_40", "thin_ellipsoid_40"])
+                                  "wall_sphere_40", "near_pair_48", "wall_plate_40", "thin_ellipsoid_40",
+                                  "stacked_plates_40", "crossing_plates_40"])
 def test_mixed_solve_within_1e8(torch_cuda, name):
     torch = torch_cuda
     p = CASES[name]
