@@ -87,6 +87,14 @@ def cases_small():
         "crossing_plates_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
         [W.plate((0.5, 0.5, 0.5), 0.4, 0.4, 16, 16, 0.0, 0.0), W.plate((0.5, 0.52, 0.475), 0.35, 0.3, 14, 12, 0.05, 0.3)])
     out["crossing_plates_40"].f = W.noise_rhs(40 ** 3, 14)
+    # a sphere cut by three walls at a corner (image-point boxes clamped on
+    # every axis), a sphere wholly outside the domain and a membrane smaller
+    # than a cell that cuts no link: the last two leave the operator unchanged
+    out["corner_outside_40"] = W.Problem(
+        "corner_outside_40", W.uniform_faces(40), W.uniform_faces(40), W.uniform_faces(40),
+        [W.sphere((1.3, 0.5, 0.5), 0.2, freq=6), W.sphere((0.97, 0.96, 0.03), 0.18, freq=8),
+         W.plate((0.5012, 0.5012, 0.5012), 0.01, 0.01, 2, 2, 0.0, 0.0)])
+    out["corner_outside_40"].f = W.noise_rhs(40 ** 3, 16)
     out["empty_box"] = W.Problem("empty_box", W.uniform_faces(16), W.uniform_faces(16), W.uniform_faces(16), [])
     out["empty_box"].f = W.manufactured_rhs(out["empty_box"].xf, out["empty_box"].yf, out["empty_box"].zf)
     return out
@@ -223,7 +231,7 @@ def test_fp64_solve_config_tolerance_c1(torch_cuda):
 
 @pytest.mark.parametrize("name", ["c1", "c2_64", "membrane_64", "mixed_bodies_48", "odd_fine", "box_odd",
                                   "wall_sphere_40", "near_pair_48", "wall_plate_40", "thin_ellipsoid_40",
-                                  "stacked_plates_40", "crossing_plates_40"])
+                                  "stacked_plates_40", "crossing_plates_40", "corner_outside_40"])
 def test_mixed_solve_within_1e8(torch_cuda, name):
     torch = torch_cuda
     p = CASES[name]
