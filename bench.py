@@ -20,6 +20,7 @@ Prints one JSON line.  Only one GPU is used: --gpus above 1 is refused.
 from __future__ import annotations
 
 import argparse
+import faulthandler
 import json
 import math
 import os
@@ -669,4 +670,8 @@ def main():
 
 
 if __name__ == "__main__":
+    # on a fatal signal: every Python thread's position (faulthandler) and,
+    # from the solve server, the faulting native thread's stack
+    faulthandler.enable()
+    os.environ.setdefault("IBM_CRASH_TRACE", "1")
     main()

@@ -449,6 +449,11 @@ void poisson_destroy(poisson_ctx *ctx);
  * against hbm_budget and the least recently used idle ones are freed when an
  * admission needs the memory.  Every solve is deterministic, so a result is
  * the same alone, in the mix and from the cache.
+ * With the environment variable IBM_CRASH_TRACE set when a server is
+ * created, a fatal SIGSEGV, SIGBUS or SIGFPE in any thread of the process
+ * writes the signal, the faulting address, the thread id and that thread's
+ * native stack to standard error before the signal goes on to the handler
+ * installed earlier or to the default action (installed once per process).
  */
 typedef struct poisson_server poisson_server;
 

@@ -21,6 +21,12 @@
 #include <mutex>
 #include <thread>
 
+#include <csignal>
+#include <cstring>
+#include <execinfo.h>
+#include <sys/syscall.h>
+#include <unistd.h>
+
 namespace ibm {
 void classify(const ibm_grid *, const ibm_body *, int, uint8_t *, ibm_class_stats *, hipStream_t);
 void build_stencils(const ibm_grid *, const ibm_body *, int, const uint8_t *, ibm_stencils **, hipStream_t,
@@ -73,6 +79,73 @@ void append_bytes(std::string &k, const T *p, size_t n)
 double now_ms(std::chrono::steady_clock::time_point t0)
 {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------- crash report
+// Opt-in (IBM_CRASH_TRACE set when a server is created): a fatal SIGSEGV,
+// SIGBUS or SIGFPE in any thread of the process first writes the signal, the
+// faulting address, the kernel thread id and that thread's native stack to
+// standard error, then passes the signal on to the disposition installed
+// before (Python's faulthandler, say, or the default action).  Installed once
+// per process.  The handler makes only async-signal-safe calls; backtrace is
+// called once at installation so that it does not load its unwinder inside
+// the handler.  A fault from stack exhaustion is not reported (no alternate
+// signal stack).
+constexpr int kTraceSigs[3] = {SIGSEGV, SIGBUS, SIGFPE};
+struct sigaction g_prev_action[3];
+
+void put_str(const char *t)
+{
+    const ssize_t r = write(2, t, strlen(t));
+    (void)r;
+}
+
+void put_num(unsigned long long v, unsigned base)
+{
+    char buf[24];
+    int n = 0;
+    do {
+        const unsigned d = (unsigned)(v % base);
+        buf[n++] = (char)(d < 10 ? '0' + d : 'a' + d - 10);
+        v /= base;
+    } while (v && n < 24);
+    char out[25];
+    for (int q = 0; q < n; ++q) out[q] = buf[n - 1 - q];
+    out[n] = 0;
+    put_str(out);
+}
+
+void crash_trace(int sig, siginfo_t *si, void *)
+{
+    put_str("[ibm] fatal signal ");
+    put_num((unsigned)sig, 10);
+    put_str(" at address 0x");
+    put_num((unsigned long long)(uintptr_t)(si ? si->si_addr : nullptr), 16);
+    put_str(" in thread ");
+    put_num((unsigned long long)syscall(SYS_gettid), 10);
+    put_str("; native stack:\n");
+    void *fr[64];
+    backtrace_symbols_fd(fr, backtrace(fr, 64), 2);
+    for (int q = 0; q < 3; ++q)
+        if (kTraceSigs[q] == sig) sigaction(sig, &g_prev_action[q], nullptr);
+    // blocked while this handler runs: taken by the previous disposition on
+    // return (a fault would also recur there)
+    raise(sig);
+}
+
+void install_crash_trace()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        void *fr[4];
+        (void)backtrace(fr, 4);
+        struct sigaction sa;
+        memset(&sa, 0, sizeof sa);
+        sa.sa_sigaction = crash_trace;
+        sa.sa_flags = SA_SIGINFO;
+        sigemptyset(&sa.sa_mask);
+        for (int q = 0; q < 3; ++q) sigaction(kTraceSigs[q], &sa, &g_prev_action[q]);
+    });
 }
 
 }  // namespace
@@ -282,6 +355,7 @@ extern "C" int32_t poisson_server_create(const poisson_server_opts *opts, poisso
 {
     return guarded([&] {
         IBM_REQUIRE(opts && out && opts->max_slots >= 1 && opts->hbm_budget > 0, IBM_EINVAL, "bad server options");
+        if (getenv("IBM_CRASH_TRACE")) install_crash_trace();
         auto *S = new poisson_server();
         S->o = *opts;
         S->t0 = std::chrono::steady_clock::now();

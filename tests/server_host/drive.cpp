@@ -3,15 +3,30 @@
 // that repeat a grid and options (set-up cache hits) and new ones (cache
 // evictions), an HBM budget small enough that admission waits.
 // usage: drive [requests] [rate per s] [budget MB] [cache entries]
+//        drive crash <address>: create a server, then store through
+//        <address> (0 in the test) from a thread of its own, so that the
+//        crash report of IBM_CRASH_TRACE can be checked on the host
 #include "ibm_poisson.h"
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <random>
 #include <thread>
 #include <vector>
 int main(int argc, char **argv)
 {
+    if (argc > 2 && !strcmp(argv[1], "crash")) {
+        poisson_server_opts so{(size_t)1 << 26, 4, 0, 0};
+        poisson_server *S = nullptr;
+        if (poisson_server_create(&so, &S)) { printf("create failed\n"); return 1; }
+        volatile int *bad = reinterpret_cast<volatile int *>((uintptr_t)strtoull(argv[2], nullptr, 0));
+        std::thread([bad] { *bad = 1; }).join();
+        poisson_server_destroy(S);
+        printf("no crash\n");
+        return 0;
+    }
     const int nreq = argc > 1 ? atoi(argv[1]) : 3000;
     const double rate = argc > 2 ? atof(argv[2]) : 2000.0;
     const size_t mb = argc > 3 ? (size_t)atoi(argv[3]) : 64;
