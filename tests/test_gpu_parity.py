@@ -244,6 +244,40 @@ def test_mixed_solve_within_1e8(torch_cuda, name):
     assert rel(x.cpu().numpy(), xo) < 1e-8
 
 
+def test_mixed_fp64_fallback(torch_cuda):
+    """The refinement's FP64 fallback.  With each inner solve capped at 4
+    iterations and asked for 5e-11 (inner_tol 1e-12), the first FP32 solve
+    stops unconverged (about 2e-8); the next refinement step sees that and
+    finishes the remaining residual with an FP64 BiCGSTAB, still inside one
+    refinement step.  The result meets tol and the oracle and repeats bit for
+    bit.  On membrane_64 the same cap leaves the FP64 fallback short of its
+    target: the solve reports the iteration limit, again the same way each
+    time."""
+    import paper_2605_04335_amd as P
+    torch = torch_cuda
+    p = CASES["c1"]
+    say("mixed fallback", "c1")
+    xo, _, _, _ = oracle.solve_problem(orc("c1"), p.f, tol=1e-13)
+    _, _, sol, _ = gpu_setup(torch, p, precision="mixed", tol=1e-10, inner_tol=1e-12, max_iter=4)
+    f = torch.from_numpy(p.f).cuda()
+    x, stats = sol.solve(f)
+    assert stats.status == 0 and stats.rel_residual <= 1e-10
+    # one refinement step (its FP32 solve) and then the FP64 solve: a plain
+    # second FP32 step would have been counted as a second outer step
+    assert stats.outer_steps == 1 and stats.iterations > 4, (stats.outer_steps, stats.iterations)
+    assert rel(x.cpu().numpy(), xo) < 1e-8
+    x2, stats2 = sol.solve(f)
+    assert torch.equal(x, x2) and stats2.iterations == stats.iterations
+    p = CASES["membrane_64"]
+    say("mixed fallback", "membrane_64 (iteration limit)")
+    _, _, sol, _ = gpu_setup(torch, p, precision="mixed", tol=1e-10, inner_tol=1e-12, max_iter=4)
+    f = torch.from_numpy(p.f).cuda()
+    for _ in range(2):
+        with pytest.raises(P.IbmError) as e:
+            sol.solve(f)
+        assert e.value.code == P.IBM_ENOCONV
+
+
 def test_solve_deterministic(torch_cuda):
     torch = torch_cuda
     p = CASES["c2_64"]
