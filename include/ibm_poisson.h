@@ -120,7 +120,8 @@ typedef struct poisson_stats {
     int32_t outer_steps;     /* mixed: refinement steps taken */
     int32_t status;          /* same code as the return value */
     int32_t levels;          /* multigrid levels */
-    double rel_residual;     /* final true relative residual, FP64 */
+    double rel_residual;     /* final true relative residual, FP64 (also when the
+                                iteration limit or a breakdown ends the solve) */
     double pin_residual;     /* unpinned-operator residual at the pin (inconsistency of the RHS) */
     double solve_ms;         /* device time of the whole solve (events on the stream) */
     int64_t n_fallback;      /* ghost rows that took the first-order fallback */

@@ -1025,6 +1025,21 @@ void ensure_fp64(poisson_ctx &c)
         if (!b->p) b->alloc(c.Nt);
 }
 
+// true relative residual ||b - A x|| / ||b|| of the FP64 iterate (c.t is
+// overwritten); for FP64 solves that end without a checked residual
+double true_rel_residual(poisson_ctx &c, hipStream_t s)
+{
+    const Walk &W = c.W0;
+    k_dot2<double><<<W.nb, TPB, 0, s>>>(W, c.b.p, c.b.p, c.part.p, PSTRIDE);
+    k_fin<<<1, 1024, 0, s>>>(c.part.p, PSTRIDE, W.nb, FIN_SUM, S_TMP2, 0.0, c.sc.p);
+    int np = launch_apply<double>(c, M_PINNED, true, 2, c.x.p, c.t.p, c.b.p, nullptr, c.b.p, nullptr, s);
+    k_fin<<<1, 1024, 0, s>>>(c.part.p + PSTRIDE, PSTRIDE, np, FIN_SUM, S_TMP, 0.0, c.sc.p);
+    IBM_LAUNCH_CHECK();
+    read_scalars(c, s);
+    const double bn2 = c.hsc[S_TMP2];
+    return bn2 > 0.0 ? std::sqrt(c.hsc[S_TMP] / bn2) : 0.0;
+}
+
 // solve A x = b (assembled, in c.b, split) into c.x; returns status.  warm:
 // c.x holds an initial guess (zero on inactive slots, zero at the pin)
 int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s, bool warm = false)
@@ -1147,6 +1162,9 @@ int solve_core(poisson_ctx &c, poisson_stats *stats, hipStream_t s, bool warm = 
             IBM_LAUNCH_CHECK();
         }
     }
+    // an FP64 solve that stopped at its iteration limit or at a breakdown
+    // holds the recursively updated residual, not the true one
+    if (!c.mixed && rc != IBM_OK && std::isfinite(rel)) rel = true_rel_residual(c, s);
     if (stats) {
         stats->iterations = its;
         stats->outer_steps = outer;

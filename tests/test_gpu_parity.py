@@ -366,6 +366,34 @@ def test_error_paths(torch_cuda):
         assert e.value.code == P.IBM_EINVAL
 
 
+@pytest.mark.parametrize("name,its", [("c1", 6), ("membrane_64", 3), ("membrane_64", 6)])
+def test_unconverged_fp64_reports_true_residual(torch_cuda, name, its):
+    """An FP64 solve stopped by its iteration limit reports the true relative
+    residual of the iterate it returns (the oracle's pinned operator applied
+    to that iterate), not the recursively updated one.  On c1 after 6
+    iterations the two differ by 0.26% (1.727e-13 against 1.7315e-13), while
+    the reported value meets the oracle's to 3e-6; the bound leaves room for
+    the cancellation in b - A x at that level."""
+    import paper_2605_04335_amd as P
+    torch = torch_cuda
+    p = CASES[name]
+    say("unconverged fp64", name, its)
+    O = orc(name)
+    fl = O.flags
+    _, _, sol, _ = gpu_setup(torch, p, tol=1e-14, max_iter=its)
+    rng = np.random.default_rng(31)
+    xt = rng.uniform(-1, 1, sol.n_unknowns)
+    xt[~refpy.active_mask(fl, sol.nm)] = 0.0
+    xt[int(np.nonzero(fl & 8)[0][0])] = 0.0
+    b = oracle.apply(p.xf, p.yf, p.zf, fl, O.st, xt)
+    x, stats = sol.solve_assembled(torch.from_numpy(b).cuda(), check=False)
+    assert stats.status == P.IBM_ENOCONV and stats.iterations == its
+    x = x.cpu().numpy()
+    res = float(np.linalg.norm(b - oracle.apply(p.xf, p.yf, p.zf, fl, O.st, x)) / np.linalg.norm(b))
+    say("  reported %.6e, oracle %.6e" % (stats.rel_residual, res))
+    assert abs(stats.rel_residual - res) <= 1e-4 * res
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_caller_owned_workspace(torch_cuda, precision):
     """Scratch moved into a caller tensor gives bitwise the same solution; a
